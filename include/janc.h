@@ -1,0 +1,197 @@
+/*
+ * janc.h -- C ABI of the MI355X (gfx950) library for the per-time-step core
+ * update of the compressible reacting-flow solver of arXiv 2504.13750 (JANC).
+ *
+ * The library advances the 2-D multi-species reactive Euler equations
+ * (paper Sec. 4.1, Eq. 4.1-4.9) with the numerics of Sec. 4.2: Lax-Friedrichs
+ * flux-vector splitting with a global wave speed (Eq. 4.11), WENO5
+ * reconstruction with 3 ghost layers, the conservative difference (Eq. 4.10),
+ * third-order TVD Runge-Kutta, Newton for T from the internal energy, and the
+ * first-order point-implicit chemistry step (Eq. 4.12-4.13). Block tables carry
+ * the block-structured AMR of Sec. 3 (synchronous advance, Fig. 2b) and
+ * ensembles of independent problems.
+ *
+ * Conventions for every call:
+ *   - Arrays marked (device) are FP64 device memory owned by the caller; arrays
+ *     marked (host) are read during the call only.
+ *   - Layout is structure-of-arrays, field-major, x fastest: U[f][j][i] for a
+ *     grid, U[f][cell] for a pool. Conserved fields are
+ *     [rho, rho u, rho v, E, rho Y_1 .. rho Y_{Ns-1}] (Ns-1 = 1 for the
+ *     one-step model, none for the perfect gas); T[cell] is the temperature.
+ *   - Calls only enqueue work on the given stream (a hipStream_t passed as
+ *     void*, NULL = default stream) and return without synchronizing, except
+ *     where stated. A context is used by one host thread at a time.
+ *   - Argument, table and launch errors return a negative janc_status at once,
+ *     with a message in janc_last_error(). Numerical failures inside kernels
+ *     (rho <= 0, p <= 0, non-finite values, Newton not converged) set a sticky
+ *     device status word that janc_sync_status() reads and clears.
+ *   - No exceptions cross this interface.
+ */
+#ifndef JANC_H
+#define JANC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int janc_status;
+enum {
+    JANC_OK = 0,
+    JANC_EINVAL = -1,      /* bad argument, table or unsupported size */
+    JANC_ENOMEM = -2,      /* device allocation failed */
+    JANC_EHIP = -3,        /* HIP runtime error */
+    JANC_ENONFINITE = -4,  /* device: NaN/Inf produced */
+    JANC_ENEWTON = -5,     /* device: T Newton did not converge in 50 iterations */
+    JANC_ENEGATIVE = -6    /* device: rho, p or T not positive */
+};
+
+/* Boundary kinds (paper Sec. 4.3: user boundary functions), sides W, E, S, N. */
+enum { JANC_BC_PERIODIC = 0, JANC_BC_ZEROGRAD = 1, JANC_BC_SLIPWALL = 2, JANC_BC_DIRICHLET = 3 };
+
+/* Thermodynamic / chemistry models. */
+enum {
+    JANC_MODEL_CPG = 0,      /* calorically perfect gas, 4 fields */
+    JANC_MODEL_ONESTEP = 1,  /* one-step Arrhenius source advanced inside RK3 (Sec. 4.3 item 3), 5 fields */
+    JANC_MODEL_DETAILED = 2  /* NASA-7 + mass-action mechanism, point-implicit (Eq. 4.2-4.9, 4.12) */
+};
+
+enum { JANC_MAX_FIELDS = 16, JANC_MAX_LEVELS = 8 };
+
+/* Detailed mechanism (host arrays, copied at janc_create), SI units:
+ * M [ns] kg/mol; nasa [ns][7] single-range NASA-7 coefficients a0..a6
+ * (Eq. 4.3-4.5); A [nr] in (m^3/mol)^(order-1)/s; b [nr]; Ea [nr] J/mol
+ * (Eq. 4.8); nu_f, nu_b [nr][ns] integer stoichiometry (Eq. 4.6); tb [nr][ns]
+ * third-body efficiencies, used when has_tb[i] (Eq. 4.7); reversible [nr]:
+ * k_b = k_f / K_eq (Eq. 4.9) when set, else 0. The last species is the
+ * complement 1 - sum(Y). Supported ns: 2..12 (compiled sizes), nr <= 64. */
+typedef struct {
+    int ns, nr;
+    const double *M, *nasa, *A, *b, *Ea;
+    const int *nu_f, *nu_b;
+    const double *tb;
+    const int *has_tb, *reversible;
+} janc_mech;
+
+/* Per-problem physics: gamma and R for CPG/ONESTEP (R only scales T = p/(rho R));
+ * Q, Ea, k of the one-step model rate -k rho Y exp(-Ea/T). Ignored for DETAILED. */
+typedef struct {
+    double gamma, R, Q, Ea, k;
+} janc_physics;
+
+/* A uniform grid (or the level-0 grid of a block-table domain). ny = 1 means
+ * one-dimensional: no y sweep and no y term in the CFL bound. bc_prim[s] is
+ * the primitive state of a Dirichlet side s (layout of janc_init_state). */
+typedef struct {
+    int nx, ny;
+    double dx, dy;
+    int bc[4];
+    double bc_prim[4][JANC_MAX_FIELDS];
+} janc_grid;
+
+/* Time step: dt = cfl / max((|u|+c)/dx + (|v|+c)/dy) over solved cells, or
+ * dt_fixed when > 0; clipped so that t does not pass t_end when t_end > 0
+ * (steps after t_end leave the state unchanged). */
+typedef struct {
+    double cfl, dt_fixed, t_end;
+} janc_time;
+
+typedef struct janc_ctx janc_ctx;
+
+/* Create a context on HIP device `device` for one model. mech is required for
+ * JANC_MODEL_DETAILED and ignored otherwise. */
+janc_status janc_create(janc_ctx **out, int model, const janc_mech *mech, int device);
+void janc_destroy(janc_ctx *ctx);
+const char *janc_last_error(const janc_ctx *ctx);
+int janc_num_fields(const janc_ctx *ctx);
+
+/* Synchronizes the stream, returns and clears the sticky device status
+ * (JANC_OK or one of JANC_ENONFINITE, JANC_ENEWTON, JANC_ENEGATIVE). */
+janc_status janc_sync_status(janc_ctx *ctx, void *stream);
+
+/* Conserved state from primitives (paper Eq. 4.2): W (device) [nfields][n] is
+ *   CPG:      [rho, u, v, p]
+ *   ONESTEP:  [rho, u, v, p, Y]
+ *   DETAILED: [p, u, v, T, Y_1 .. Y_{Ns-1}]
+ * and U (device) [nfields][n], T (device) [n] receive the conserved state and
+ * the temperature. */
+janc_status janc_init_state(janc_ctx *ctx, const janc_physics *phys, long long n,
+                            const double *W, double *U, double *T, void *stream);
+
+/* nsteps steps of the full update on a uniform grid (Sec. 4.3 advance_one_step:
+ * CFL, RK3 flux stages, then chemistry for DETAILED). U (device) [nfields][ny][nx]
+ * and T (device) [ny][nx] are updated in place; T is re-solved from U at entry
+ * with the given T as the Newton warm start. t (device) [1] is advanced by each
+ * dt. dt_log (device) [nsteps] receives each dt, or may be NULL. */
+janc_status janc_step(janc_ctx *ctx, const janc_grid *grid, const janc_physics *phys,
+                      const janc_time *time, double *U, double *T, int nsteps, double *t,
+                      double *dt_log, void *stream);
+
+/* ------------------------------------------------------------------ block tables */
+/* A domain is one independent problem: a level-0 grid, its boundaries, its
+ * physics and the number of refinement levels (ratio 2, Sec. 3.1). Each domain
+ * has its own dt; all levels of a domain share it (synchronous advance, Fig. 2b). */
+typedef struct {
+    janc_grid grid;
+    janc_physics phys;
+    int nlevels;
+} janc_domain;
+
+/* A block (Sec. 3.1.3 "data" + "info"): nx x ny cells at (i0, j0) of its level's
+ * index space, stored at pool cell `offset` (x fastest). Invalid blocks are
+ * reserved space that is neither solved nor read. Levels >= 1 need origins and
+ * sizes that are multiples of 8 and sizes <= 256; level 0 must tile its domain. */
+typedef struct {
+    int domain, level, i0, j0, nx, ny;
+    long long offset;
+    int valid, pad;
+} janc_block;
+
+typedef struct janc_plan janc_plan;
+
+enum {
+    JANC_PLAN_DEFAULT = 0,
+    JANC_PLAN_PER_BLOCK = 1,   /* one launch per block and stage (comparison form) */
+    JANC_PLAN_NO_GRAPH = 2     /* launch kernels directly instead of a captured hipGraph */
+};
+
+/* Validate a block table and build its device work lists (blocks, level maps,
+ * coarse-fine ring masks, tiles, restriction lists). Blocks and domains are
+ * host arrays; pool_cells is the pool length. Synchronous. */
+janc_status janc_plan_create(janc_ctx *ctx, int ndomains, const janc_domain *domains,
+                             int nblocks, const janc_block *blocks, long long pool_cells,
+                             int flags, janc_plan **out);
+void janc_plan_destroy(janc_plan *plan);
+
+/* Per-plan tile shape (autotuner hook): 0 = automatic, else tile width in cells
+ * for 2-D blocks (16 or 32 or 64; height = 256 / width). Synchronous. */
+janc_status janc_plan_set_tile(janc_plan *plan, int tile_width);
+
+/* nsteps steps over a block table (Alg. 2 with synchronous advance and Alg. 3
+ * per stage): per domain dt; per (domain, level) alpha; ring cells of levels >= 1
+ * take the coarser level's value at the same stage; after each step coarse
+ * cells under finer blocks become the mean of their four children (finest level
+ * first) and ring cells are refilled. U_pool (device) [nfields][pool],
+ * T_pool (device) [pool], t (device) [ndomains]. */
+janc_status janc_step_blocks(janc_ctx *ctx, janc_plan *plan, const janc_time *time,
+                             double *U_pool, double *T_pool, int nsteps, double *t,
+                             void *stream);
+
+/* ------------------------------------------------------------------ adjoint */
+/* Discrete adjoint (the exact gradient of the discrete map) of nsteps steps of
+ * janc_step for the one-step model with a fixed dt (time->dt_fixed > 0), in the
+ * sense of the adjoint method of Sec. 6.1 (Eq. 6.1-6.5) applied to the discrete
+ * trajectory. Loss = sum_{n=1..N} dt * sum_q w_q * p(U^n at cell probe_cell[q]).
+ * W0 (device) [5][ny][nx] are initial primitives [rho, u, v, p, Y]; the state is
+ * checkpointed every ckpt_every steps and recomputed inside each segment.
+ * Outputs (device): loss[1], dL_dW0 [5][ny][nx], dL_dtheta[2] = {dL/dQ, dL/dEa}
+ * (Q enters through the equation of state and the initial energy). probe_cell
+ * and probe_w are host arrays of nprobes entries. */
+janc_status janc_adjoint(janc_ctx *ctx, const janc_grid *grid, const janc_physics *phys,
+                         const janc_time *time, const double *W0, int nsteps, int ckpt_every,
+                         int nprobes, const int *probe_cell, const double *probe_w,
+                         double *loss, double *dL_dW0, double *dL_dtheta, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JANC_H */

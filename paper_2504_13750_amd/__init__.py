@@ -1,0 +1,240 @@
+"""MI355X-native per-time-step core update of the JANC reacting-flow solver.
+
+Python binding of the C ABI in include/janc.h (libjanc.so, hand-written HIP
+kernels for gfx950). This module only marshals arguments: torch tensors supply
+device memory (FP64, SoA, x fastest) and the stream; every step of the update
+runs in the library's kernels. There is no CPU fallback: without the built
+library every call raises.
+
+Paper: "JANC: A cost-effective, differentiable compressible reacting flow
+solver featured with JAX-based adaptive mesh refinement", arXiv 2504.13750.
+"""
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import LibraryMissing
+
+CPG, ONESTEP, DETAILED = 0, 1, 2
+BC_PERIODIC, BC_ZEROGRAD, BC_SLIPWALL, BC_DIRICHLET = 0, 1, 2, 3
+PLAN_DEFAULT, PLAN_PER_BLOCK, PLAN_NO_GRAPH = 0, 1, 2
+STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONFINITE", -5: "ENEWTON",
+          -6: "ENEGATIVE"}
+
+BLOCK_DTYPE = np.dtype([
+    ("domain", np.int32), ("level", np.int32), ("i0", np.int32), ("j0", np.int32),
+    ("nx", np.int32), ("ny", np.int32), ("offset", np.int64), ("valid", np.int32),
+    ("pad", np.int32),
+])
+
+
+class JancError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"janc error {code} ({STATUS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dptr(x, numel=None, name="array"):
+    """Device pointer of a contiguous FP64 CUDA tensor (or None)."""
+    if x is None:
+        return None
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 tensor on a HIP device")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and x.numel() != numel:
+        raise ValueError(f"{name} has {x.numel()} elements, expected {numel}")
+    return C.c_void_p(x.data_ptr())
+
+
+# ------------------------------------------------------------------ structs
+def make_grid(nx, ny, dx, dy, bc, bc_prim=None):
+    g = L.janc_grid()
+    g.nx, g.ny, g.dx, g.dy = int(nx), int(ny), float(dx), float(dy)
+    for s in range(4):
+        g.bc[s] = int(bc[s])
+        if bc_prim is not None and bc_prim[s] is not None:
+            v = np.asarray(bc_prim[s], dtype=np.float64)
+            for f in range(len(v)):
+                g.bc_prim[s][f] = float(v[f])
+    return g
+
+
+def make_physics(gamma=1.4, R=1.0, Q=0.0, Ea=0.0, k=0.0):
+    return L.janc_physics(float(gamma), float(R), float(Q), float(Ea), float(k))
+
+
+def make_time(cfl=0.5, dt_fixed=0.0, t_end=0.0):
+    return L.janc_time(float(cfl), float(dt_fixed), float(t_end))
+
+
+def grid_of(case):
+    return make_grid(case.nx, case.ny, case.dx, case.dy, case.bc, case.bc_prim)
+
+
+def physics_of(obj):
+    return make_physics(obj.gamma, obj.R, obj.Q, obj.Ea, obj.k)
+
+
+def time_of(case, **over):
+    kw = dict(cfl=case.cfl, dt_fixed=case.dt_fixed, t_end=case.t_end)
+    kw.update(over)
+    return make_time(**kw)
+
+
+def domains_of(bcase):
+    arr = (L.janc_domain * len(bcase.domains))()
+    for d, dom in enumerate(bcase.domains):
+        arr[d].grid = make_grid(dom.nx, dom.ny, dom.dx, dom.dy, dom.bc, dom.bc_prim)
+        arr[d].phys = physics_of(dom)
+        arr[d].nlevels = int(dom.nlevels)
+    return arr
+
+
+class _Mech:
+    def __init__(self, mech):
+        def f64(a):
+            return np.ascontiguousarray(a, dtype=np.float64)
+
+        def i32(a):
+            return np.ascontiguousarray(a, dtype=np.int32)
+        self.keep = [f64(mech.M), f64(mech.nasa), f64(mech.A), f64(mech.b), f64(mech.Ea),
+                     i32(mech.nu_f), i32(mech.nu_b), f64(mech.tb), i32(mech.has_tb),
+                     i32(mech.reversible)]
+        k = self.keep
+        pd = lambda a: a.ctypes.data_as(L.PD)
+        pi = lambda a: a.ctypes.data_as(L.PI)
+        self.s = L.janc_mech(len(mech.M), len(mech.A), pd(k[0]), pd(k[1]), pd(k[2]), pd(k[3]),
+                             pd(k[4]), pi(k[5]), pi(k[6]), pd(k[7]), pi(k[8]), pi(k[9]))
+
+
+# ------------------------------------------------------------------ context
+class Plan:
+    def __init__(self, ctx, handle, ndom, pool_cells):
+        self.ctx, self.h, self.ndom, self.pool_cells = ctx, handle, ndom, pool_cells
+
+    def set_tile(self, width):
+        self.ctx._check(L.lib().janc_plan_set_tile(self.h, int(width)))
+
+    def close(self):
+        if self.h:
+            L.lib().janc_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """A library context (janc_create) on one HIP device for one model."""
+
+    def __init__(self, model, mech=None, device=0):
+        lib = L.lib()
+        self.model = int(model)
+        self._mech = _Mech(mech) if mech is not None else None
+        h = C.c_void_p()
+        st = lib.janc_create(C.byref(h), self.model,
+                             C.byref(self._mech.s) if self._mech else None, int(device))
+        if st != 0:
+            raise JancError(st, "janc_create failed")
+        self.h = h
+        self.device = int(device)
+
+    @property
+    def nfields(self):
+        return int(L.lib().janc_num_fields(self.h))
+
+    def _check(self, st):
+        if st != 0:
+            msg = L.lib().janc_last_error(self.h)
+            raise JancError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lib().janc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync_status(self, stream=None):
+        self._check(L.lib().janc_sync_status(self.h, C.c_void_p(_stream_handle(stream))))
+
+    def init_state(self, phys, W, stream=None):
+        """Primitive W [nfields, ...] (device) -> (U, T) (new device tensors)."""
+        torch = _torch()
+        n = W[0].numel()
+        U = torch.empty_like(W)
+        T = torch.empty(W.shape[1:], dtype=torch.float64, device=W.device)
+        self._check(L.lib().janc_init_state(self.h, C.byref(phys), C.c_longlong(n),
+                                            _dptr(W, name="W"), _dptr(U), _dptr(T),
+                                            C.c_void_p(_stream_handle(stream))))
+        return U, T
+
+    def step(self, grid, phys, time, U, T, nsteps, t, dt_log=None, stream=None):
+        n = grid.nx * grid.ny
+        self._check(L.lib().janc_step(self.h, C.byref(grid), C.byref(phys), C.byref(time),
+                                      _dptr(U, self.nfields * n, "U"), _dptr(T, n, "T"),
+                                      int(nsteps), _dptr(t, 1, "t"),
+                                      _dptr(dt_log, None, "dt_log"),
+                                      C.c_void_p(_stream_handle(stream))))
+
+    def plan(self, domains, blocks, pool_cells, flags=PLAN_DEFAULT):
+        blocks = np.ascontiguousarray(blocks, dtype=BLOCK_DTYPE)
+        h = C.c_void_p()
+        self._check(L.lib().janc_plan_create(self.h, len(domains), domains, len(blocks),
+                                             blocks.ctypes.data_as(C.c_void_p),
+                                             C.c_longlong(int(pool_cells)), int(flags),
+                                             C.byref(h)))
+        return Plan(self, h, len(domains), int(pool_cells))
+
+    def step_blocks(self, plan, time, U, T, nsteps, t, stream=None):
+        self._check(L.lib().janc_step_blocks(self.h, plan.h, C.byref(time),
+                                             _dptr(U, self.nfields * plan.pool_cells, "U"),
+                                             _dptr(T, plan.pool_cells, "T"), int(nsteps),
+                                             _dptr(t, plan.ndom, "t"),
+                                             C.c_void_p(_stream_handle(stream))))
+
+    def adjoint(self, grid, phys, time, W0, nsteps, ckpt_every, probe_cell, probe_w,
+                stream=None):
+        """Returns (loss, dL/dW0, dL/dtheta) as device tensors ([1], [5, ny, nx], [2])."""
+        torch = _torch()
+        pc = np.ascontiguousarray(probe_cell, dtype=np.int32)
+        pw = np.ascontiguousarray(probe_w, dtype=np.float64)
+        loss = torch.zeros(1, dtype=torch.float64, device=W0.device)
+        gW = torch.zeros_like(W0)
+        gth = torch.zeros(2, dtype=torch.float64, device=W0.device)
+        self._check(L.lib().janc_adjoint(self.h, C.byref(grid), C.byref(phys), C.byref(time),
+                                         _dptr(W0, 5 * grid.nx * grid.ny, "W0"), int(nsteps),
+                                         int(ckpt_every), len(pc), pc.ctypes.data_as(L.PI),
+                                         pw.ctypes.data_as(L.PD), _dptr(loss), _dptr(gW),
+                                         _dptr(gth), C.c_void_p(_stream_handle(stream))))
+        return loss, gW, gth
+
+
+def load():
+    """Load the HIP library (raises LibraryMissing when it is not built)."""
+    return L.lib()

@@ -1,0 +1,689 @@
+// janc_api.hip -- host runtime behind the C ABI of include/janc.h: contexts,
+// block-table plans (validation, level maps, coarse-fine ring masks, tiles,
+// restriction lists), call sequencing and hipGraph capture of whole steps.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/janc.h"
+#include "janc_internal.h"
+
+using namespace janc;
+
+struct janc_plan;
+
+struct janc_ctx {
+    int device = 0;
+    int model = 0;
+    int ns = 0;
+    int nU = 0;
+    DevMech hmech{};
+    DevMech* dmech = nullptr;
+    unsigned* dstatus = nullptr;
+    std::string err;
+    // cached plan for janc_step (uniform grids)
+    janc_plan* uplan = nullptr;
+    janc_grid ugrid{};
+    janc_physics uphys{};
+};
+
+struct GraphKey {
+    const double *U, *T, *t, *dt_log;
+    int cap;
+    double cfl, dt_fixed, t_end;
+    bool operator==(const GraphKey& o) const {
+        return U == o.U && T == o.T && t == o.t && dt_log == o.dt_log && cap == o.cap &&
+               cfl == o.cfl && dt_fixed == o.dt_fixed && t_end == o.t_end;
+    }
+};
+
+struct janc_plan {
+    janc_ctx* ctx = nullptr;
+    int flags = 0;
+    int ndom = 0, nblk = 0;
+    long long pool = 0;
+    int nunits = 0;
+    int tile_w = 16;
+    int kind_mask = 0;            // bit 0: 2-D tiles present, bit 1: 1-D tiles present
+    int maxlev = 0;
+    std::vector<DevDomain> hdom;
+    std::vector<DevBlock> hblk;   // valid blocks only (device block ids)
+    std::vector<int> hmap;
+    std::vector<Tile> htiles;
+    std::vector<int> tile_first, tile_count;   // per valid block
+    std::vector<std::vector<int>> fine;        // per level >= 1: valid block ids
+    std::vector<int> ring_blocks;
+    std::vector<double> hdir;
+    // device
+    DevDomain* ddom = nullptr;
+    DevBlock* dblk = nullptr;
+    int* dmap = nullptr;
+    Tile* dtiles = nullptr;
+    double* ddir = nullptr;
+    unsigned long long* dred = nullptr;
+    int red_stride = 0;
+    double* ddt = nullptr;
+    int* dstep = nullptr;
+    int* dfine = nullptr;          // concatenated fine lists
+    std::vector<int> fine_off;
+    int* dring = nullptr;
+    double *U1 = nullptr, *U2 = nullptr, *T1 = nullptr, *T2 = nullptr;
+    // graph cache
+    bool have_graph = false;
+    GraphKey gkey{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+int n_fields(int model, int ns) { return model == CPG ? 4 : model == ONESTEP ? 5 : ns + 3; }
+
+janc_status fail(janc_ctx* c, janc_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+janc_status hipfail(janc_ctx* c, hipError_t e, const char* what) {
+    return fail(c, JANC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, expr, what)                      \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hipfail(ctx, _e, what); \
+    } while (0)
+
+template <class T> janc_status dalloc(janc_ctx* c, T** p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+    if (e != hipSuccess) return fail(c, JANC_ENOMEM, "hipMalloc of %zu bytes failed", n * sizeof(T));
+    return JANC_OK;
+}
+
+template <class T> janc_status upload(janc_ctx* c, T** p, const std::vector<T>& v) {
+    janc_status st = dalloc(c, p, v.size());
+    if (st) return st;
+    if (!v.empty()) HIPCHK(c, hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+    return JANC_OK;
+}
+
+void plan_free(janc_plan* p) {
+    if (!p) return;
+    if (p->gexec) hipGraphExecDestroy(p->gexec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    void* ptrs[] = {p->ddom, p->dblk, p->dmap, p->dtiles, p->ddir, p->dred, p->ddt, p->dstep,
+                    p->dfine, p->dring, p->U1, p->U2, p->T1, p->T2};
+    for (void* q : ptrs)
+        if (q) hipFree(q);
+    delete p;
+}
+
+// --------------------------------------------------------------- mechanism
+janc_status build_mech(janc_ctx* c, const janc_mech* m) {
+    if (!m || m->ns < 2 || m->ns > MAXS || m->nr < 0 || m->nr > MAXR)
+        return fail(c, JANC_EINVAL, "mechanism sizes out of range (ns 2..%d, nr 0..%d)", MAXS, MAXR);
+    if (!model_supported(DETAILED, m->ns))
+        return fail(c, JANC_EINVAL, "no kernels compiled for ns = %d (available: 2, 9)", m->ns);
+    DevMech& d = c->hmech;
+    std::memset(&d, 0, sizeof(d));
+    d.ns = m->ns;
+    d.nr = m->nr;
+    for (int k = 0; k < m->ns; ++k) {
+        if (!(m->M[k] > 0.0)) return fail(c, JANC_EINVAL, "molar mass of species %d not positive", k);
+        d.invM[k] = 1.0 / m->M[k];
+        d.Rk[k] = RU / m->M[k];
+        for (int q = 0; q < 7; ++q) d.nasa[k][q] = m->nasa[7 * k + q];
+    }
+    for (int i = 0; i < m->nr; ++i) {
+        d.lnA[i] = (m->A[i] > 0.0) ? std::log(m->A[i]) : -INFINITY;
+        d.b[i] = m->b[i];
+        d.EaR[i] = m->Ea[i] / RU;
+        d.rev[i] = m->reversible[i] ? 1 : 0;
+        d.has_tb[i] = m->has_tb[i] ? 1 : 0;
+        int nf = 0, nb = 0, ds = 0;
+        for (int q = 0; q < 4; ++q) d.lf[i][q] = d.lb[i][q] = m->ns;
+        for (int j = 0; j < m->ns; ++j) {
+            const int f = m->nu_f[i * m->ns + j], b = m->nu_b[i * m->ns + j];
+            if (f < 0 || b < 0) return fail(c, JANC_EINVAL, "negative stoichiometry in reaction %d", i);
+            for (int q = 0; q < f; ++q) {
+                if (nf >= MAXLIST) return fail(c, JANC_EINVAL, "reaction %d has more than %d reactant molecules", i, MAXLIST);
+                d.lf[i][nf++] = j;
+            }
+            for (int q = 0; q < b; ++q) {
+                if (nb >= MAXLIST) return fail(c, JANC_EINVAL, "reaction %d has more than %d product molecules", i, MAXLIST);
+                d.lb[i][nb++] = j;
+            }
+            d.dnu[i][j] = b - f;
+            d.Mdnu[i][j] = m->M[j] * (double)(b - f);
+            d.tb[i][j] = m->tb[i * m->ns + j];
+            ds += b - f;
+        }
+        d.dnsum[i] = ds;
+    }
+    janc_status st = dalloc(c, &c->dmech, 1);
+    if (st) return st;
+    HIPCHK(c, hipMemcpy(c->dmech, &d, sizeof(d), hipMemcpyHostToDevice), "hipMemcpy mech");
+    return JANC_OK;
+}
+
+// --------------------------------------------------------------- plan building
+struct LevelMap {
+    int w8 = 0, h8 = 0, off = 0;
+};
+
+janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, const janc_block* blocks,
+                       long long pool, int flags, janc_plan** out) {
+    *out = nullptr;
+    if (nd < 1 || nb < 1 || pool < 1 || !doms || !blocks)
+        return fail(c, JANC_EINVAL, "empty block table");
+    std::unique_ptr<janc_plan, void (*)(janc_plan*)> P(new janc_plan(), plan_free);
+    P->ctx = c;
+    P->flags = flags;
+    P->ndom = nd;
+    P->pool = pool;
+    const int nU = c->nU;
+    // ---- domains
+    std::vector<std::vector<LevelMap>> lm(nd);
+    int map_total = 0, slot = 0, ndir = 0;
+    for (int d = 0; d < nd; ++d) {
+        const janc_domain& D = doms[d];
+        const janc_grid& g = D.grid;
+        DevDomain h{};
+        if (g.nx < 3 || g.ny < 1 || (g.ny > 1 && g.ny < 3))
+            return fail(c, JANC_EINVAL, "domain %d: grid %dx%d too small (need >= 3 cells per active direction)", d, g.nx, g.ny);
+        if (!(g.dx > 0.0) || !(g.dy > 0.0)) return fail(c, JANC_EINVAL, "domain %d: dx, dy must be positive", d);
+        if (D.nlevels < 1 || D.nlevels > MAXL) return fail(c, JANC_EINVAL, "domain %d: nlevels out of range", d);
+        if (D.nlevels > 1 && g.ny == 1) return fail(c, JANC_EINVAL, "domain %d: refinement needs a 2-D grid", d);
+        for (int s = 0; s < 4; ++s)
+            if (g.bc[s] < 0 || g.bc[s] > 3) return fail(c, JANC_EINVAL, "domain %d: bad boundary kind", d);
+        if ((g.bc[0] == BC_PERIODIC) != (g.bc[1] == BC_PERIODIC) ||
+            (g.ny > 1 && (g.bc[2] == BC_PERIODIC) != (g.bc[3] == BC_PERIODIC)))
+            return fail(c, JANC_EINVAL, "domain %d: periodic boundaries must pair", d);
+        if (c->model != DETAILED && !(D.phys.gamma > 1.0))
+            return fail(c, JANC_EINVAL, "domain %d: gamma must exceed 1", d);
+        h.nx0 = g.nx;
+        h.ny0 = g.ny;
+        h.twod = g.ny > 1 ? 1 : 0;
+        h.nlevels = D.nlevels;
+        for (int s = 0; s < 4; ++s) {
+            h.bc[s] = g.bc[s];
+            h.dir[s] = -1;
+            if (g.bc[s] == BC_DIRICHLET && (s < 2 || h.twod)) h.dir[s] = ndir++;
+        }
+        h.dx0 = g.dx;
+        h.dy0 = g.dy;
+        h.gamma = D.phys.gamma;
+        h.R = D.phys.R;
+        h.Q = D.phys.Q;
+        h.Ea = D.phys.Ea;
+        h.k = D.phys.k;
+        h.slot0 = slot;
+        slot += D.nlevels;
+        lm[d].resize(D.nlevels);
+        for (int l = 0; l < D.nlevels; ++l) {
+            const int W = g.nx << l, H = h.twod ? (g.ny << l) : 1;
+            lm[d][l].w8 = (W + 7) / 8;
+            lm[d][l].h8 = (H + 7) / 8;
+            lm[d][l].off = map_total;
+            h.map_off[l] = map_total;
+            h.map_w[l] = lm[d][l].w8;
+            map_total += lm[d][l].w8 * lm[d][l].h8;
+        }
+        P->maxlev = std::max(P->maxlev, D.nlevels - 1);
+        P->hdom.push_back(h);
+    }
+    P->nunits = slot;
+    for (int d = 0; d < nd; ++d) P->hdom[d].cfl_slot = 2 * slot + d;
+    P->hmap.assign(map_total, -1);
+    // ---- blocks
+    std::vector<int> count(nd * MAXL, 0);
+    for (int b = 0; b < nb; ++b)
+        if (blocks[b].valid) {
+            if (blocks[b].domain < 0 || blocks[b].domain >= nd) return fail(c, JANC_EINVAL, "block %d: bad domain", b);
+            if (blocks[b].level < 0 || blocks[b].level >= doms[blocks[b].domain].nlevels)
+                return fail(c, JANC_EINVAL, "block %d: bad level", b);
+            count[blocks[b].domain * MAXL + blocks[b].level]++;
+        }
+    for (int b = 0; b < nb; ++b) {
+        const janc_block& r = blocks[b];
+        if (!r.valid) continue;
+        const DevDomain& D = P->hdom[r.domain];
+        const int W = D.nx0 << r.level, H = D.twod ? (D.ny0 << r.level) : 1;
+        if (r.nx < 1 || r.ny < 1 || r.i0 < 0 || r.j0 < 0 || r.i0 + r.nx > W || r.j0 + r.ny > H)
+            return fail(c, JANC_EINVAL, "block %d outside its level", b);
+        if (!D.twod && (r.ny != 1 || r.j0 != 0)) return fail(c, JANC_EINVAL, "block %d: 1-D domain blocks have ny = 1", b);
+        if (r.offset < 0 || r.offset + (long long)r.nx * r.ny > pool)
+            return fail(c, JANC_EINVAL, "block %d: pool range out of bounds", b);
+        const bool multi = count[r.domain * MAXL + r.level] > 1;
+        if (r.level > 0 || multi) {
+            auto ok8 = [](int o, int n, int lim) { return (o % 8 == 0) && (n % 8 == 0 || o + n == lim); };
+            if (!ok8(r.i0, r.nx, W) || (D.twod && !ok8(r.j0, r.ny, H)))
+                return fail(c, JANC_EINVAL, "block %d: origin/size not multiples of 8", b);
+        }
+        if (r.level > 0 && (r.nx > 256 || r.ny > 256 || r.nx % 8 || r.ny % 8))
+            return fail(c, JANC_EINVAL, "block %d: refined blocks need sizes multiple of 8 and <= 256", b);
+        DevBlock h{};
+        h.domain = r.domain;
+        h.level = r.level;
+        h.i0 = r.i0;
+        h.j0 = r.j0;
+        h.nx = r.nx;
+        h.ny = r.ny;
+        h.offset = r.offset;
+        h.fine_child = (r.level + 1 < D.nlevels) ? 1 : 0;
+        const int id = (int)P->hblk.size();
+        const LevelMap& L = lm[r.domain][r.level];
+        for (int y = r.j0 / 8; y < (r.j0 + r.ny + 7) / 8; ++y)
+            for (int x = r.i0 / 8; x < (r.i0 + r.nx + 7) / 8; ++x) {
+                int& m = P->hmap[L.off + y * L.w8 + x];
+                if (m >= 0) return fail(c, JANC_EINVAL, "block %d overlaps another block", b);
+                m = id;
+            }
+        P->hblk.push_back(h);
+    }
+    // pool ranges of valid blocks must not overlap
+    {
+        std::vector<std::pair<long long, long long>> rg;
+        for (auto& h : P->hblk) rg.push_back({h.offset, h.offset + (long long)h.nx * h.ny});
+        std::sort(rg.begin(), rg.end());
+        for (size_t q = 1; q < rg.size(); ++q)
+            if (rg[q].first < rg[q - 1].second) return fail(c, JANC_EINVAL, "blocks share pool cells");
+    }
+    for (int d = 0; d < nd; ++d) {
+        const LevelMap& L = lm[d][0];
+        for (int q = 0; q < L.w8 * L.h8; ++q)
+            if (P->hmap[L.off + q] < 0) return fail(c, JANC_EINVAL, "domain %d: level 0 does not tile the domain", d);
+    }
+    // ---- ring masks: an 8-cell segment of a side faces uncovered in-domain cells
+    auto covered = [&](int d, int l, int I8, int J8) -> int {
+        const DevDomain& D = P->hdom[d];
+        const LevelMap& L = lm[d][l];
+        if (I8 < 0 || I8 >= L.w8) {
+            if (D.bc[0] != BC_PERIODIC) return 1;
+            I8 = (I8 + L.w8) % L.w8;
+        }
+        if (J8 < 0 || J8 >= L.h8) {
+            if (D.bc[2] != BC_PERIODIC) return 1;
+            J8 = (J8 + L.h8) % L.h8;
+        }
+        return P->hmap[L.off + J8 * L.w8 + I8] >= 0;
+    };
+    for (auto& h : P->hblk) {
+        if (h.level == 0) continue;
+        const int x8 = h.i0 / 8, y8 = h.j0 / 8, w8 = h.nx / 8, h8 = h.ny / 8;
+        for (int g = 0; g < h8; ++g) {
+            if (!covered(h.domain, h.level, x8 - 1, y8 + g)) h.ring[0] |= 1u << g;
+            if (!covered(h.domain, h.level, x8 + w8, y8 + g)) h.ring[1] |= 1u << g;
+        }
+        for (int g = 0; g < w8; ++g) {
+            if (!covered(h.domain, h.level, x8 + g, y8 - 1)) h.ring[2] |= 1u << g;
+            if (!covered(h.domain, h.level, x8 + g, y8 + h8)) h.ring[3] |= 1u << g;
+        }
+    }
+    // ---- proper nesting: coarse footprints of refined blocks are solved (non-ring) cells
+    auto ring_cell = [](const DevBlock& B, int li, int lj) {
+        return (li < 3 && ((B.ring[0] >> (lj >> 3)) & 1u)) || (li >= B.nx - 3 && ((B.ring[1] >> (lj >> 3)) & 1u)) ||
+               (lj < 3 && ((B.ring[2] >> (li >> 3)) & 1u)) || (lj >= B.ny - 3 && ((B.ring[3] >> (li >> 3)) & 1u));
+    };
+    P->fine.assign(P->maxlev + 1, std::vector<int>());
+    for (int id = 0; id < (int)P->hblk.size(); ++id) {
+        const DevBlock& h = P->hblk[id];
+        if (h.level == 0) continue;
+        const LevelMap& L = lm[h.domain][h.level - 1];
+        for (int cj = h.j0 / 2; cj < (h.j0 + h.ny) / 2; ++cj)
+            for (int ci = h.i0 / 2; ci < (h.i0 + h.nx) / 2; ++ci) {
+                const int pb = P->hmap[L.off + (cj >> 3) * L.w8 + (ci >> 3)];
+                if (pb < 0) return fail(c, JANC_EINVAL, "refined block at (%d,%d) level %d is not nested in level %d", h.i0, h.j0, h.level, h.level - 1);
+                const DevBlock& B = P->hblk[pb];
+                if (B.level > 0 && ring_cell(B, ci - B.i0, cj - B.j0))
+                    return fail(c, JANC_EINVAL, "refined block at (%d,%d) level %d covers coarse-fine ring cells of level %d", h.i0, h.j0, h.level, h.level - 1);
+            }
+        P->fine[h.level].push_back(id);
+        if (h.ring[0] | h.ring[1] | h.ring[2] | h.ring[3]) P->ring_blocks.push_back(id);
+    }
+    // ---- Dirichlet rows (conserved state + T), converted on the device
+    P->hdir.assign((size_t)std::max(ndir, 1) * (MAXF + 1), 0.0);
+    janc_status st;
+    if ((st = dalloc(c, &P->ddir, P->hdir.size()))) return st;
+    {
+        double* dW = nullptr;
+        if ((st = dalloc(c, &dW, MAXF))) return st;
+        for (int d = 0; d < nd; ++d)
+            for (int s = 0; s < 4; ++s) {
+                const int row = P->hdom[d].dir[s];
+                if (row < 0) continue;
+                hipError_t e = hipMemcpy(dW, doms[d].grid.bc_prim[s], sizeof(double) * nU, hipMemcpyHostToDevice);
+                if (e == hipSuccess)
+                    e = launch_prim_to_cons(c->model, c->ns, c->dmech, doms[d].phys.gamma, doms[d].phys.R,
+                                            doms[d].phys.Q, 1, dW, P->ddir + (size_t)row * (MAXF + 1),
+                                            P->ddir + (size_t)row * (MAXF + 1) + MAXF, 1, 1, nullptr);
+                if (e == hipSuccess) e = hipDeviceSynchronize();
+                if (e != hipSuccess) {
+                    hipFree(dW);
+                    return hipfail(c, e, "Dirichlet state");
+                }
+            }
+        hipFree(dW);
+    }
+    P->ndom = nd;
+    P->nblk = (int)P->hblk.size();
+    // ---- device tables and workspaces
+    if ((st = upload(c, &P->ddom, P->hdom))) return st;
+    if ((st = upload(c, &P->dblk, P->hblk))) return st;
+    if ((st = upload(c, &P->dmap, P->hmap))) return st;
+    std::vector<int> fl;
+    for (int l = 0; l <= P->maxlev; ++l) {
+        P->fine_off.push_back((int)fl.size());
+        fl.insert(fl.end(), P->fine[l].begin(), P->fine[l].end());
+    }
+    if ((st = upload(c, &P->dfine, fl))) return st;
+    if ((st = upload(c, &P->dring, P->ring_blocks))) return st;
+    P->red_stride = 2 * P->nunits + nd;
+    if ((st = dalloc(c, &P->dred, (size_t)3 * P->red_stride))) return st;
+    if ((st = dalloc(c, &P->ddt, nd))) return st;
+    if ((st = dalloc(c, &P->dstep, 1))) return st;
+    if ((st = dalloc(c, &P->U1, (size_t)nU * pool))) return st;
+    if ((st = dalloc(c, &P->U2, (size_t)nU * pool))) return st;
+    if ((st = dalloc(c, &P->T1, (size_t)pool))) return st;
+    if ((st = dalloc(c, &P->T2, (size_t)pool))) return st;
+    *out = P.release();
+    return JANC_OK;
+}
+
+// Tiles of every valid block for the plan's 2-D tile width (1-D blocks: 256-cell rows).
+janc_status build_tiles(janc_ctx* c, janc_plan* P) {
+    P->htiles.clear();
+    P->tile_first.assign(P->nblk, 0);
+    P->tile_count.assign(P->nblk, 0);
+    P->kind_mask = 0;
+    const int TX = P->tile_w, TY = 256 / TX;
+    for (int id = 0; id < P->nblk; ++id) {
+        const DevBlock& h = P->hblk[id];
+        P->tile_first[id] = (int)P->htiles.size();
+        if (!P->hdom[h.domain].twod) {
+            for (int x = 0; x < h.nx; x += 256) P->htiles.push_back(Tile{id, x, 0, 1});
+            P->kind_mask |= 2;
+        } else {
+            for (int y = 0; y < h.ny; y += TY)
+                for (int x = 0; x < h.nx; x += TX) P->htiles.push_back(Tile{id, x, y, TX << 8});
+            P->kind_mask |= 1;
+        }
+        P->tile_count[id] = (int)P->htiles.size() - P->tile_first[id];
+    }
+    if (P->dtiles) hipFree(P->dtiles);
+    P->dtiles = nullptr;
+    return upload(c, &P->dtiles, P->htiles);
+}
+
+StageArgs base_args(janc_plan* P, const janc_time* tm, double* U, double* T, double* t,
+                    double* dt_log, int cap) {
+    StageArgs a{};
+    a.dom = P->ddom;
+    a.blk = P->dblk;
+    a.maps = P->dmap;
+    a.tiles = P->dtiles;
+    a.ntiles = (int)P->htiles.size();
+    a.dirU = P->ddir;
+    a.mech = P->ctx->dmech;
+    a.U0 = U;
+    a.pool = P->pool;
+    a.red = Reduce{P->dred, P->red_stride, P->nunits, P->ndom, 0};
+    a.ndom = P->ndom;
+    a.dt = P->ddt;
+    a.t = t;
+    a.dt_log = dt_log;
+    a.step = P->dstep;
+    a.dt_log_cap = cap;
+    a.tm = TimeArgs{tm->cfl, tm->dt_fixed, tm->t_end};
+    a.status = P->ctx->dstatus;
+    (void)T;
+    return a;
+}
+
+// Enqueue one full step (3 stages, chemistry, restriction, ring refill).
+hipError_t enqueue_step(janc_plan* P, const StageArgs& base, double* U, double* T, hipStream_t s) {
+    janc_ctx* c = P->ctx;
+    const int model = c->model, ns = c->ns;
+    double* Uin[3] = {U, P->U1, P->U2};
+    double* Uout[3] = {P->U1, P->U2, U};
+    double* Tin[3] = {T, P->T1, P->T2};
+    double* Tout[3] = {P->T1, P->T2, T};
+    hipError_t e = hipSuccess;
+    for (int st = 1; st <= 3 && e == hipSuccess; ++st) {
+        StageArgs a = base;
+        a.stage = st;
+        a.Uin = Uin[st - 1];
+        a.Uout = Uout[st - 1];
+        a.Tin = Tin[st - 1];
+        a.Tout = Tout[st - 1];
+        a.reduce_out = (st == 3 && model == DETAILED) ? 0 : 1;
+        if (P->flags & JANC_PLAN_PER_BLOCK) {
+            for (int id = 0; id < P->nblk && e == hipSuccess; ++id)
+                e = launch_stage(model, ns, P->kind_mask, P->tile_w, a, P->tile_first[id], P->tile_count[id], s);
+        } else {
+            e = launch_stage(model, ns, P->kind_mask, P->tile_w, a, 0, a.ntiles, s);
+        }
+    }
+    StageArgs a = base;
+    a.stage = 3;
+    a.Uin = U;
+    a.Uout = U;
+    a.Tin = T;
+    a.Tout = T;
+    if (e == hipSuccess && model == DETAILED) e = launch_chem(model, ns, P->tile_w, a, s);
+    for (int l = P->maxlev; l >= 1 && e == hipSuccess; --l)
+        e = launch_restrict(model, ns, a, P->dfine + P->fine_off[l], (int)P->fine[l].size(), s);
+    if (e == hipSuccess && !P->ring_blocks.empty())
+        e = launch_ring_fill(model, ns, a, P->dring, (int)P->ring_blocks.size(), s);
+    return e;
+}
+
+void drop_graph(janc_plan* P) {
+    if (P->gexec) hipGraphExecDestroy(P->gexec);
+    if (P->graph) hipGraphDestroy(P->graph);
+    P->gexec = nullptr;
+    P->graph = nullptr;
+    P->have_graph = false;
+}
+
+// Call entry (T re-solved from U, maxima for the first stage), then nsteps
+// steps: replayed from a captured hipGraph of one step, or launched directly.
+janc_status run_steps(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U, double* T,
+                      int nsteps, double* t, double* dt_log, hipStream_t s) {
+    HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    const StageArgs base = base_args(P, tm, U, T, t, dt_log, nsteps);
+    HIPCHK(c, launch_clear_reduce(base.red, -1, s), "clear launch");
+    HIPCHK(c, launch_zero_int(P->dstep, s), "counter launch");
+    StageArgs a0 = base;
+    a0.Uin = U;
+    a0.Tin = T;
+    a0.Tout = T;
+    HIPCHK(c, launch_init(c->model, c->ns, P->tile_w, a0, s), "init launch");
+    if (nsteps == 0) return JANC_OK;
+    if (P->flags & JANC_PLAN_NO_GRAPH) {
+        for (int n = 0; n < nsteps; ++n) HIPCHK(c, enqueue_step(P, base, U, T, s), "step launch");
+        return JANC_OK;
+    }
+    const GraphKey key{U, T, t, dt_log, nsteps, tm->cfl, tm->dt_fixed, tm->t_end};
+    if (!P->have_graph || !(P->gkey == key)) {
+        drop_graph(P);
+        hipStream_t cs;
+        HIPCHK(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+            hipError_t e2 = enqueue_step(P, base, U, T, cs);
+            e = hipStreamEndCapture(cs, &P->graph);
+            if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0);
+        hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+            drop_graph(P);
+            return hipfail(c, e, "graph capture");
+        }
+        P->gkey = key;
+        P->have_graph = true;
+    }
+    for (int n = 0; n < nsteps; ++n) HIPCHK(c, hipGraphLaunch(P->gexec, s), "hipGraphLaunch");
+    return JANC_OK;
+}
+
+// Plan of a uniform grid: one domain, one level-0 block covering it; cached.
+janc_status uniform_plan(janc_ctx* c, const janc_grid* g, const janc_physics* ph) {
+    if (c->uplan && std::memcmp(&c->ugrid, g, sizeof(*g)) == 0 &&
+        std::memcmp(&c->uphys, ph, sizeof(*ph)) == 0)
+        return JANC_OK;
+    plan_free(c->uplan);
+    c->uplan = nullptr;
+    janc_domain D;
+    D.grid = *g;
+    D.phys = *ph;
+    D.nlevels = 1;
+    janc_block B{0, 0, 0, 0, g->nx, g->ny, 0, 1, 0};
+    janc_plan* P = nullptr;
+    janc_status st = build_plan(c, 1, &D, 1, &B, (long long)g->nx * g->ny, 0, &P);
+    if (st) return st;
+    if (g->ny > 1 && g->nx >= 64 && g->ny < 16) P->tile_w = 64;
+    else if (g->ny > 1 && g->nx >= 32 && g->ny < 32) P->tile_w = 32;
+    st = build_tiles(c, P);
+    if (st) {
+        plan_free(P);
+        return st;
+    }
+    c->uplan = P;
+    c->ugrid = *g;
+    c->uphys = *ph;
+    return JANC_OK;
+}
+
+}  // namespace
+
+// =============================================================== C ABI
+extern "C" {
+
+janc_status janc_create(janc_ctx** out, int model, const janc_mech* mech, int device) {
+    if (!out) return JANC_EINVAL;
+    *out = nullptr;
+    std::unique_ptr<janc_ctx> c(new janc_ctx());
+    if (model < CPG || model > DETAILED) return JANC_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return JANC_EHIP;
+    if (hipSetDevice(device) != hipSuccess) return JANC_EHIP;
+    c->device = device;
+    c->model = model;
+    if (model == DETAILED) {
+        janc_status st = build_mech(c.get(), mech);
+        if (st) return st;
+        c->ns = mech->ns;
+    }
+    c->nU = n_fields(model, c->ns);
+    if (dalloc(c.get(), &c->dstatus, 1)) return JANC_ENOMEM;
+    if (hipMemset(c->dstatus, 0, sizeof(unsigned)) != hipSuccess) return JANC_EHIP;
+    *out = c.release();
+    return JANC_OK;
+}
+
+void janc_destroy(janc_ctx* c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    plan_free(c->uplan);
+    if (c->dmech) hipFree(c->dmech);
+    if (c->dstatus) hipFree(c->dstatus);
+    delete c;
+}
+
+const char* janc_last_error(const janc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int janc_num_fields(const janc_ctx* c) { return c ? c->nU : 0; }
+
+janc_status janc_sync_status(janc_ctx* c, void* stream) {
+    if (!c) return JANC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipStreamSynchronize(s), "hipStreamSynchronize");
+    unsigned st = 0;
+    HIPCHK(c, hipMemcpy(&st, c->dstatus, sizeof(st), hipMemcpyDeviceToHost), "status read");
+    HIPCHK(c, hipMemset(c->dstatus, 0, sizeof(unsigned)), "status clear");
+    if (st & STB_NONFINITE) return fail(c, JANC_ENONFINITE, "non-finite value produced on the device");
+    if (st & STB_NEWTON) return fail(c, JANC_ENEWTON, "temperature Newton did not converge");
+    if (st & STB_NEGATIVE) return fail(c, JANC_ENEGATIVE, "density, pressure or temperature not positive");
+    return JANC_OK;
+}
+
+janc_status janc_init_state(janc_ctx* c, const janc_physics* ph, long long n, const double* W,
+                            double* U, double* T, void* stream) {
+    if (!c || !ph || n < 0 || (n > 0 && (!W || !U || !T))) return fail(c, JANC_EINVAL, "bad arguments");
+    hipError_t e = launch_prim_to_cons(c->model, c->ns, c->dmech, ph->gamma, ph->R, ph->Q, n, W, U, T,
+                                       n, n, (hipStream_t)stream);
+    if (e != hipSuccess) return hipfail(c, e, "init_state launch");
+    return JANC_OK;
+}
+
+janc_status janc_plan_create(janc_ctx* c, int nd, const janc_domain* doms, int nb,
+                             const janc_block* blocks, long long pool, int flags, janc_plan** out) {
+    if (!c || !out) return JANC_EINVAL;
+    janc_status st = build_plan(c, nd, doms, nb, blocks, pool, flags, out);
+    if (st) return st;
+    st = build_tiles(c, *out);
+    if (st) {
+        plan_free(*out);
+        *out = nullptr;
+    }
+    return st;
+}
+
+void janc_plan_destroy(janc_plan* p) { plan_free(p); }
+
+janc_status janc_plan_set_tile(janc_plan* p, int w) {
+    if (!p) return JANC_EINVAL;
+    if (w == 0) w = 16;
+    if (w != 16 && w != 32 && w != 64) return fail(p->ctx, JANC_EINVAL, "tile width must be 16, 32 or 64");
+    p->tile_w = w;
+    if (p->have_graph) {
+        hipGraphExecDestroy(p->gexec);
+        hipGraphDestroy(p->graph);
+        p->gexec = nullptr;
+        p->graph = nullptr;
+        p->have_graph = false;
+    }
+    return build_tiles(p->ctx, p);
+}
+
+janc_status janc_step_blocks(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U, double* T,
+                             int nsteps, double* t, void* stream) {
+    if (!c || !P || !tm || !U || !T || !t || nsteps < 0) return fail(c, JANC_EINVAL, "bad arguments");
+    if (P->ctx != c) return fail(c, JANC_EINVAL, "plan belongs to another context");
+    if (!(tm->dt_fixed > 0.0) && !(tm->cfl > 0.0)) return fail(c, JANC_EINVAL, "need cfl > 0 or dt_fixed > 0");
+    return run_steps(c, P, tm, U, T, nsteps, t, nullptr, (hipStream_t)stream);
+}
+
+janc_status janc_step(janc_ctx* c, const janc_grid* g, const janc_physics* ph, const janc_time* tm,
+                      double* U, double* T, int nsteps, double* t, double* dt_log, void* stream) {
+    if (!c || !g || !ph || !tm || !U || !T || !t || nsteps < 0) return fail(c, JANC_EINVAL, "bad arguments");
+    if (!(tm->dt_fixed > 0.0) && !(tm->cfl > 0.0)) return fail(c, JANC_EINVAL, "need cfl > 0 or dt_fixed > 0");
+    janc_status st = uniform_plan(c, g, ph);
+    if (st) return st;
+    return run_steps(c, c->uplan, tm, U, T, nsteps, t, dt_log, (hipStream_t)stream);
+}
+
+janc_status janc_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
+                         const janc_time* tm, const double* W0, int nsteps, int ckpt_every,
+                         int nprobes, const int* probe_cell, const double* probe_w, double* loss,
+                         double* dL_dW0, double* dL_dtheta, void* stream) {
+    (void)g; (void)ph; (void)tm; (void)W0; (void)nsteps; (void)ckpt_every; (void)nprobes;
+    (void)probe_cell; (void)probe_w; (void)loss; (void)dL_dW0; (void)dL_dtheta; (void)stream;
+    return fail(c, JANC_EINVAL, "adjoint kernels are not part of this build yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// janc_internal.h -- device data layouts shared by the kernels and the host
+// runtime of the JANC step library (gfx950). Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace janc {
+
+constexpr int MAXF = 16;        // conserved fields (4 + species - 1)
+constexpr int MAXL = 8;         // refinement levels per domain
+constexpr int MAXS = 12;        // species
+constexpr int MAXR = 64;        // reactions
+constexpr int MAXLIST = 3;      // reactant / product molecules per reaction
+constexpr double RU = 8.314472;     // J/(mol K), paper Sec. 4.1
+constexpr double PATM = 101325.0;   // Pa, Eq. 4.9
+
+enum Model { CPG = 0, ONESTEP = 1, DETAILED = 2 };
+enum { BC_PERIODIC = 0, BC_ZEROGRAD = 1, BC_SLIPWALL = 2, BC_DIRICHLET = 3 };
+
+// Sticky status bits written by kernels.
+enum : unsigned { STB_NONFINITE = 1u, STB_NEWTON = 2u, STB_NEGATIVE = 4u };
+
+// A domain: level-0 grid + boundaries + physics + per-level block maps.
+struct DevDomain {
+    int nx0, ny0, nlevels, twod;
+    int bc[4];
+    int dir[4];               // row of the Dirichlet table per side (-1 = none)
+    int map_off[MAXL];        // offset of each level's block map (8x8-cell granularity)
+    int map_w[MAXL];
+    int slot0;                // alpha slot of level 0 (slot0 + level)
+    int cfl_slot;             // index of this domain's CFL slot
+    double dx0, dy0;
+    double gamma, R, Q, Ea, k;
+};
+
+// A valid block. ring[s]: bit g set when the 8-cell segment g of side s
+// (W, E, S, N) faces in-domain cells not covered at this level; the 3 cell
+// layers along such a segment are coarse-fine ring cells.
+struct DevBlock {
+    int domain, level, i0, j0, nx, ny;
+    long long offset;
+    unsigned ring[4];
+    int fine_child;           // 1 if a finer level exists in this domain
+    int pad;
+};
+
+// One tile of a block: origin (x0, y0) in block-local cells.
+struct Tile {
+    int block, x0, y0, kind;  // kind 0 = 2-D tile shape, 1 = 1-D row tile
+};
+
+// Detailed mechanism in the layout the kernels read (uniform loads).
+struct DevMech {
+    int ns, nr;
+    int pad[2];
+    double invM[MAXS];
+    double Rk[MAXS];                   // R_u / M_k
+    double nasa[MAXS][7];
+    double lnA[MAXR], b[MAXR], EaR[MAXR];
+    int rev[MAXR], has_tb[MAXR], dnsum[MAXR], pad2[MAXR];
+    int lf[MAXR][4], lb[MAXR][4];      // reactant / product species lists, padded with ns (= 1.0)
+    int dnu[MAXR][MAXS];
+    double Mdnu[MAXR][MAXS];           // M_k (nu_b - nu_f), production weights
+    double tb[MAXR][MAXS];
+};
+
+// Reduction slots (three rotating buffers of `stride` 64-bit words): per
+// (domain, level) unit the maxima of |u|+c and |v|+c (Eq. 4.11), per domain
+// the CFL bound max((|u|+c)/dx + (|v|+c)/dy). Non-negative doubles are stored
+// by bit pattern, so an unsigned integer max is the floating-point max.
+struct Reduce {
+    unsigned long long* buf;
+    int stride;
+    int nunits;
+    int ndom;
+    int pad;
+};
+
+struct TimeArgs {
+    double cfl, dt_fixed, t_end;
+};
+
+struct StageArgs {
+    const DevDomain* dom;
+    const DevBlock* blk;
+    const int* maps;
+    const Tile* tiles;
+    int ntiles;
+    int stage;                // 1..3
+    const double* dirU;       // Dirichlet rows: MAXF conserved values then T
+    const DevMech* mech;
+    const double* U0;         // step start state U^n
+    const double* Uin;        // stage input U^(s-1)
+    double* Uout;             // stage output U^(s)
+    const double* Tin;
+    double* Tout;
+    long long pool;           // field stride of the pools
+    Reduce red;
+    int reduce_out;           // accumulate maxima of the output state
+    int ndom;
+    double* dt;               // [ndom] this step's dt
+    double* t;                // [ndom] time
+    double* dt_log;           // [capacity][ndom] or null
+    int* step;                // device step counter (for dt_log)
+    int dt_log_cap;
+    TimeArgs tm;
+    unsigned* status;
+};
+
+// Launchers implemented in janc_kernels.hip.
+hipError_t launch_clear_reduce(const Reduce& r, int which, hipStream_t s);
+hipError_t launch_zero_int(int* p, hipStream_t s);
+hipError_t launch_stage(int model, int ns, int kind_mask, int tile_w, const StageArgs& a,
+                        int first_tile, int ntiles, hipStream_t s);
+hipError_t launch_init(int model, int ns, int tile_w, const StageArgs& a, hipStream_t s);
+hipError_t launch_chem(int model, int ns, int tile_w, const StageArgs& a, hipStream_t s);
+hipError_t launch_restrict(int model, int ns, const StageArgs& a, const int* fine_blocks,
+                           int nfine, hipStream_t s);
+hipError_t launch_ring_fill(int model, int ns, const StageArgs& a, const int* ring_blocks,
+                            int nring, hipStream_t s);
+hipError_t launch_prim_to_cons(int model, int ns, const DevMech* mech, double gamma, double R,
+                               double Q, long long n, const double* W, double* U, double* T,
+                               long long stride_in, long long stride_out, hipStream_t s);
+bool model_supported(int model, int ns);
+
+}  // namespace janc

@@ -1,0 +1,961 @@
+// janc_kernels.hip -- gfx950 kernels of the JANC per-time-step update.
+//
+// One RK stage is one launch over a list of tiles (a tile is up to 16x16,
+// 32x8 or 64x4 cells of one block, or 256 cells of a one-dimensional block),
+// one 256-thread workgroup per tile. Per tile:
+//   phase 0  every cell of the tile plus 3 halo layers (cross-shaped; corners
+//            are not needed by the dimension-by-dimension sweeps) is fetched
+//            from its source -- the same block, a neighbouring block, the
+//            coarser level for coarse-fine ring cells, or a boundary rule --
+//            and its primitives are kept in registers;
+//   phase 1  per conserved component: Lax-Friedrichs split fluxes F+/F- and
+//            G+/G- (Eq. 4.11) go to LDS, WENO5 interface fluxes (Sec. 4.2)
+//            are reconstructed from LDS, and each owned cell forms the
+//            conservative difference (Eq. 4.10) and its Shu-Osher RK stage;
+//   phase 2  T of the new state (Newton warm-started from the previous stage
+//            for the NASA-7 model, Sec. 4.2), status checks, and the maxima of
+//            |u|+c, |v|+c and the CFL bound for the next stage, reduced per
+//            wavefront and published with one 64-bit atomic max per workgroup.
+// Nothing here is a dense contraction, so there is no MFMA: the work is FP64
+// VALU arithmetic on values staged through LDS.
+#include "janc_internal.h"
+
+namespace janc {
+
+constexpr int WG = 256;
+constexpr double WENO_EPS = 1e-6;
+
+// ------------------------------------------------------------------ small helpers
+__device__ __forceinline__ double sq(double x) { return x * x; }
+
+__device__ __forceinline__ double slot_get(const Reduce& r, int buf, int idx) {
+    return __longlong_as_double((long long)r.buf[(size_t)buf * r.stride + idx]);
+}
+
+__device__ __forceinline__ void slot_max(const Reduce& r, int buf, int idx, double v) {
+    // v >= 0: the bit pattern orders like the value
+    atomicMax(&r.buf[(size_t)buf * r.stride + idx], (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Workgroup max of three values; thread 0 publishes them.
+__device__ __forceinline__ void publish_max3(const Reduce& r, int buf, int i0, int i1, int i2,
+                                             double v0, double v1, double v2, double* scratch) {
+    v0 = wave_max(v0);
+    v1 = wave_max(v1);
+    v2 = wave_max(v2);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        scratch[3 * w + 0] = v0;
+        scratch[3 * w + 1] = v1;
+        scratch[3 * w + 2] = v2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m0 = scratch[0], m1 = scratch[1], m2 = scratch[2];
+        for (int q = 1; q < WG / 64; ++q) {
+            m0 = fmax(m0, scratch[3 * q]);
+            m1 = fmax(m1, scratch[3 * q + 1]);
+            m2 = fmax(m2, scratch[3 * q + 2]);
+        }
+        if (m0 > 0.0) slot_max(r, buf, i0, m0);
+        if (m1 > 0.0) slot_max(r, buf, i1, m1);
+        if (m2 > 0.0) slot_max(r, buf, i2, m2);
+    }
+}
+
+// Coarse-fine ring test for block-local cell (li, lj) (segment masks per side).
+__device__ __forceinline__ bool ring_at(const DevBlock& B, int li, int lj) {
+    const unsigned sx = (unsigned)(lj >> 3) & 31u, sy = (unsigned)(li >> 3) & 31u;
+    return (li < 3 && ((B.ring[0] >> sx) & 1u)) || (li >= B.nx - 3 && ((B.ring[1] >> sx) & 1u)) ||
+           (lj < 3 && ((B.ring[2] >> sy) & 1u)) || (lj >= B.ny - 3 && ((B.ring[3] >> sy) & 1u));
+}
+
+// Effective source of level-`lev` cell (I, J) of domain D: boundary rule first,
+// then the covering block of that level, or the coarser level where the cell is
+// uncovered or a ring cell. Returns a pool cell (>= 0) or -(1 + Dirichlet row);
+// fl gets bit 0 / bit 1 when x / y momentum must be mirrored.
+__device__ long long resolve(const StageArgs& a, const DevDomain& D, int lev, int I, int J,
+                             unsigned& fl) {
+    const int W = D.nx0 << lev, H = D.twod ? (D.ny0 << lev) : 1;
+    if (I < 0 || I >= W) {
+        const int side = (I < 0) ? 0 : 1;
+        switch (D.bc[side]) {
+            case BC_PERIODIC: I = (I < 0) ? I + W : I - W; break;
+            case BC_ZEROGRAD: I = (I < 0) ? 0 : W - 1; break;
+            case BC_SLIPWALL: I = (I < 0) ? -I - 1 : 2 * W - 1 - I; fl ^= 1u; break;
+            default: return -(1ll + D.dir[side]);
+        }
+    }
+    if (J < 0 || J >= H) {
+        const int side = (J < 0) ? 2 : 3;
+        switch (D.bc[side]) {
+            case BC_PERIODIC: J = (J < 0) ? J + H : J - H; break;
+            case BC_ZEROGRAD: J = (J < 0) ? 0 : H - 1; break;
+            case BC_SLIPWALL: J = (J < 0) ? -J - 1 : 2 * H - 1 - J; fl ^= 2u; break;
+            default: return -(1ll + D.dir[side]);
+        }
+    }
+    for (;;) {
+        const int b = a.maps[D.map_off[lev] + (J >> 3) * D.map_w[lev] + (I >> 3)];
+        if (b >= 0) {
+            const DevBlock& B = a.blk[b];
+            const int li = I - B.i0, lj = J - B.j0;
+            if (!ring_at(B, li, lj)) return B.offset + (long long)lj * B.nx + li;
+        }
+        // level 0 tiles the domain and has no ring cells, so this ends
+        --lev;
+        I >>= 1;
+        J >>= 1;
+    }
+}
+
+template <int NU>
+__device__ __forceinline__ void fetch(const StageArgs& a, long long src, unsigned fl,
+                                      const double* Uarr, const double* Tarr, double (&u)[NU],
+                                      double& T) {
+    if (src >= 0) {
+#pragma unroll
+        for (int f = 0; f < NU; ++f) u[f] = Uarr[(size_t)f * a.pool + src];
+        T = Tarr[src];
+    } else {
+        const double* r = a.dirU + (size_t)(-src - 1) * (MAXF + 1);
+#pragma unroll
+        for (int f = 0; f < NU; ++f) u[f] = r[f];
+        T = r[MAXF];
+    }
+    if (fl & 1u) u[1] = -u[1];
+    if (fl & 2u) u[2] = -u[2];
+}
+
+// Velocities and pressure of a stencil cell (Eq. 4.2; T from storage for NASA-7).
+template <int M, int NU>
+__device__ __forceinline__ void halo_prims(const double (&u)[NU], double T, const DevDomain& D,
+                                           const DevMech* mech, double& vx, double& vy,
+                                           double& p) {
+    const double ir = 1.0 / u[0];
+    vx = u[1] * ir;
+    vy = u[2] * ir;
+    if constexpr (M == DETAILED) {
+        double s = 0.0, r = 0.0;
+#pragma unroll
+        for (int k = 0; k < NU - 4; ++k) {
+            s += u[4 + k];
+            r += u[4 + k] * mech->invM[k];
+        }
+        r += (u[0] - s) * mech->invM[NU - 4];
+        p = RU * r * T;
+    } else {
+        double e = u[3] * ir - 0.5 * (vx * vx + vy * vy);
+        if constexpr (M == ONESTEP) e -= u[4] * ir * D.Q;
+        p = (D.gamma - 1.0) * u[0] * e;
+    }
+}
+
+// Newton for T from the internal energy on mixture NASA coefficients
+// (Y fixed during the solve, so the species sums are formed once).
+template <int NS>
+__device__ __forceinline__ unsigned newton_T(const double (&Y)[NS], double e, const DevMech* m,
+                                             double& T, double& cv, double& Rmix) {
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0, b4 = 0.0, b5 = 0.0;
+    Rmix = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const double w = Y[k] * m->Rk[k];
+        Rmix += w;
+        b0 += w * m->nasa[k][0];
+        b1 += w * m->nasa[k][1];
+        b2 += w * m->nasa[k][2];
+        b3 += w * m->nasa[k][3];
+        b4 += w * m->nasa[k][4];
+        b5 += w * m->nasa[k][5];
+    }
+    const double c0 = b0 - Rmix, c1 = 0.5 * b1, c2 = b2 * (1.0 / 3.0), c3 = 0.25 * b3,
+                 c4 = 0.2 * b4;
+    unsigned st = STB_NEWTON;
+    for (int it = 0; it < 50; ++it) {
+        const double ec = T * (c0 + T * (c1 + T * (c2 + T * (c3 + T * c4)))) + b5;
+        const double cvv = c0 + T * (b1 + T * (b2 + T * (b3 + T * b4)));
+        const double dT = (ec - e) / cvv;
+        T -= dT;
+        if (!(fabs(dT) <= 1e-12 * fabs(T))) {
+            if (!isfinite(T)) { st = STB_NONFINITE; break; }
+            continue;
+        }
+        st = 0u;
+        break;
+    }
+    cv = c0 + T * (b1 + T * (b2 + T * (b3 + T * b4)));
+    return st;
+}
+
+// State of an owned cell after an update: T (closed form or Newton from Tprev),
+// sound speed and velocities; returns status bits.
+template <int M, int NU>
+__device__ __forceinline__ unsigned owner_state(const double (&u)[NU], double Tprev,
+                                                const DevDomain& D, const DevMech* mech,
+                                                double& T, double& c, double& vx, double& vy) {
+    const double rho = u[0];
+    if (!isfinite(rho)) return STB_NONFINITE;
+    if (!(rho > 0.0)) return STB_NEGATIVE;
+    const double ir = 1.0 / rho;
+    vx = u[1] * ir;
+    vy = u[2] * ir;
+    const double e = u[3] * ir - 0.5 * (vx * vx + vy * vy);
+    double p, gam;
+    unsigned st = 0u;
+    if constexpr (M == DETAILED) {
+        constexpr int NS = NU - 3;
+        double Y[NS];
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS - 1; ++k) {
+            Y[k] = u[4 + k] * ir;
+            s += Y[k];
+        }
+        Y[NS - 1] = 1.0 - s;
+        T = Tprev;
+        double cv, Rmix;
+        st = newton_T<NS>(Y, e, mech, T, cv, Rmix);
+        p = rho * Rmix * T;
+        gam = (cv + Rmix) / cv;
+    } else {
+        double ee = e;
+        if constexpr (M == ONESTEP) ee -= u[4] * ir * D.Q;
+        p = (D.gamma - 1.0) * rho * ee;
+        T = p / (rho * D.R);
+        gam = D.gamma;
+    }
+    if (!isfinite(p) || !isfinite(T)) return st | STB_NONFINITE;
+    if (!(p > 0.0) || !(T > 0.0)) return st | STB_NEGATIVE;
+    c = sqrt(gam * p * ir);
+    return st;
+}
+
+// WENO5-JS at i+1/2 from f_{i-2..i+2}: the weighted average of the three
+// candidate stencils in common-denominator form (one division).
+__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
+    const double q0 = 2.0 * a - 7.0 * b + 11.0 * c;
+    const double q1 = -b + 5.0 * c + 2.0 * d;
+    const double q2 = 2.0 * c + 5.0 * d - e;
+    const double t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
+    const double t1 = b - 2.0 * c + d, u1 = b - d;
+    const double t2 = c - 2.0 * d + e, u2 = 3.0 * c - 4.0 * d + e;
+    const double s0 = sq(WENO_EPS + ((13.0 / 12.0) * t0 * t0 + 0.25 * u0 * u0));
+    const double s1 = sq(WENO_EPS + ((13.0 / 12.0) * t1 * t1 + 0.25 * u1 * u1));
+    const double s2 = sq(WENO_EPS + ((13.0 / 12.0) * t2 * t2 + 0.25 * u2 * u2));
+    const double w0 = 0.1 * (s1 * s2), w1 = 0.6 * (s0 * s2), w2 = 0.3 * (s0 * s1);
+    return (w0 * q0 + w1 * q1 + w2 * q2) / (6.0 * (w0 + w1 + w2));
+}
+
+__device__ __forceinline__ double rk_combine(int stage, double u0, double us, double L, double dt) {
+    if (stage == 1) return u0 + dt * L;
+    if (stage == 2) return 0.75 * u0 + 0.25 * (us + dt * L);
+    return (1.0 / 3.0) * u0 + (2.0 / 3.0) * (us + dt * L);
+}
+
+__device__ __forceinline__ double step_dt(const StageArgs& a, int d, int bin) {
+    double dt;
+    if (a.tm.dt_fixed > 0.0) {
+        dt = a.tm.dt_fixed;
+    } else {
+        dt = a.tm.cfl / slot_get(a.red, bin, 2 * a.red.nunits + d);
+    }
+    if (a.tm.t_end > 0.0) {
+        const double rem = a.tm.t_end - a.t[d];
+        if (!(rem > 0.0)) dt = 0.0;
+        else if (dt > rem) dt = rem;
+    }
+    return dt;
+}
+
+// Is level-`lev` cell (I, J) of D under a valid block of level lev+1?
+__device__ __forceinline__ bool covered_by_finer(const StageArgs& a, const DevDomain& D, int lev,
+                                                 int I, int J) {
+    if (lev + 1 >= D.nlevels) return false;
+    const int I2 = 2 * I, J2 = 2 * J;
+    return a.maps[D.map_off[lev + 1] + (J2 >> 3) * D.map_w[lev + 1] + (I2 >> 3)] >= 0;
+}
+
+// Per-launch bookkeeping done by workgroup 0: rotate reduction buffers, dt and t.
+__device__ void stage_bookkeeping(const StageArgs& a, int owner_launch) {
+    const int s = a.stage;
+    const int bclear = (s + 1) % 3;
+    for (int q = threadIdx.x; q < a.red.stride; q += WG) a.red.buf[(size_t)bclear * a.red.stride + q] = 0ull;
+    if (!owner_launch) return;
+    if (s == 1) {
+        const int step = *a.step;
+        for (int d = threadIdx.x; d < a.ndom; d += WG) {
+            const double dt = step_dt(a, d, 0);
+            a.dt[d] = dt;
+            if (a.dt_log && step < a.dt_log_cap) a.dt_log[(size_t)step * a.ndom + d] = dt;
+        }
+    }
+}
+
+__device__ void step_finish(const StageArgs& a) {
+    for (int d = threadIdx.x; d < a.ndom; d += WG) a.t[d] = a.t[d] + a.dt[d];
+    if (threadIdx.x == 0) *a.step = *a.step + 1;
+}
+
+// ------------------------------------------------------------------ the stage tile
+template <int TX, int TY>
+struct Geom {
+    static constexpr bool TWO = TY > 1;
+    static constexpr int GY = TWO ? 3 : 0;
+    static constexpr int PW = TX + 6, PH = TY + 2 * GY, NP = PW * PH, NPT = (NP + WG - 1) / WG;
+    static constexpr int NXS = PW * TY;
+    static constexpr int NYS = TWO ? TX * (TY + 6) : 0;
+    static constexpr int NIX = (TX + 1) * TY;
+    static constexpr int NIY = TWO ? TX * (TY + 1) : 0;
+    static constexpr int NC = TX * TY;
+    // LDS doubles: fpx, fmx, fpy, fmy, fhx, fhy, T of cells, explicit source, scratch
+    static constexpr int LDS = 2 * NXS + 2 * NYS + NIX + NIY + 2 * NC + 16;
+};
+
+template <int M, int NU, int TX, int TY>
+__device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
+    using G = Geom<TX, TY>;
+    static_assert(TX * TY == WG, "one owned cell per thread");
+    double* fpx = smem;
+    double* fmx = fpx + G::NXS;
+    double* fpy = fmx + G::NXS;
+    double* fmy = fpy + G::NYS;
+    double* fhx = fmy + G::NYS;
+    double* fhy = fhx + G::NIX;
+    double* tcell = fhy + G::NIY;
+    double* scell = tcell + G::NC;
+    double* scratch = scell + G::NC;
+
+    const int tid = threadIdx.x;
+    const DevBlock B = a.blk[tile.block];
+    const DevDomain& D = a.dom[B.domain];
+    const int lev = B.level;
+    const int stage = a.stage;
+    const int bin = stage - 1, bout = stage % 3;
+    const double dt = (stage == 1) ? step_dt(a, B.domain, 0) : a.dt[B.domain];
+    if (!(dt > 0.0)) return;   // finished domain: state unchanged
+    const double dxl = D.dx0 / (double)(1 << lev), dyl = D.dy0 / (double)(1 << lev);
+    const double idx = 1.0 / dxl, idy = 1.0 / dyl;
+    const int slot = D.slot0 + lev;
+    const double ax = slot_get(a.red, bin, 2 * slot);
+    const double ay = slot_get(a.red, bin, 2 * slot + 1);
+    const int tw = min(TX, B.nx - tile.x0), th = min(TY, B.ny - tile.y0);
+
+    // ---------------- phase 0: fetch the tile and its halo, primitives in registers
+    double ur[G::NPT][NU];
+    double vxr[G::NPT], vyr[G::NPT], pr[G::NPT];
+    bool needx[G::NPT], needy[G::NPT];
+#pragma unroll
+    for (int q = 0; q < G::NPT; ++q) {
+        const int p = tid + q * WG;
+        needx[q] = needy[q] = false;
+        vxr[q] = vyr[q] = pr[q] = 0.0;
+#pragma unroll
+        for (int f = 0; f < NU; ++f) ur[q][f] = 0.0;
+        if (p < G::NP) {
+            const int pj = p / G::PW, pi = p - pj * G::PW;
+            const int li = pi - 3, lj = pj - G::GY;
+            needx[q] = (lj >= 0 && lj < th) && (li >= -3 && li < tw + 3);
+            needy[q] = G::TWO && (li >= 0 && li < tw) && (lj >= -3 && lj < th + 3);
+            if (needx[q] || needy[q]) {
+                const int bi = tile.x0 + li, bj = tile.y0 + lj;
+                long long src;
+                unsigned fl = 0u;
+                if (bi >= 0 && bi < B.nx && bj >= 0 && bj < B.ny && !ring_at(B, bi, bj))
+                    src = B.offset + (long long)bj * B.nx + bi;
+                else
+                    src = resolve(a, D, lev, B.i0 + bi, B.j0 + bj, fl);
+                double T;
+                fetch<NU>(a, src, fl, a.Uin, a.Tin, ur[q], T);
+                halo_prims<M, NU>(ur[q], T, D, a.mech, vxr[q], vyr[q], pr[q]);
+                if (li >= 0 && li < TX && lj >= 0 && lj < TY) {
+                    tcell[lj * TX + li] = T;
+                    if constexpr (M == ONESTEP) {
+                        const double Tc = pr[q] / (ur[q][0] * D.R);
+                        scell[lj * TX + li] = -D.k * ur[q][4] * exp(-D.Ea / Tc);
+                    }
+                }
+            }
+        }
+    }
+
+    // owned cell
+    const int oli = tid % TX, olj = tid / TX;
+    const int obi = tile.x0 + oli, obj = tile.y0 + olj;
+    const bool own = (oli < tw) && (olj < th) && !ring_at(B, obi, obj);
+    const long long oc = B.offset + (long long)obj * B.nx + obi;
+    double unew[NU];
+
+    // ---------------- phase 1: per component split fluxes, WENO5, RK update
+#pragma unroll
+    for (int f = 0; f < NU; ++f) {
+#pragma unroll
+        for (int q = 0; q < G::NPT; ++q) {
+            const int p = tid + q * WG;
+            const int pj = p / G::PW, pi = p - pj * G::PW;
+            const double uf = ur[q][f];
+            if (needx[q]) {
+                double F = uf * vxr[q];
+                if (f == 1) F += pr[q];
+                if (f == 3) F = (uf + pr[q]) * vxr[q];
+                const int xi = (pj - G::GY) * G::PW + pi;
+                fpx[xi] = 0.5 * (F + ax * uf);
+                fmx[xi] = 0.5 * (F - ax * uf);
+            }
+            if constexpr (G::TWO) {
+                if (needy[q]) {
+                    double Gf = uf * vyr[q];
+                    if (f == 2) Gf += pr[q];
+                    if (f == 3) Gf = (uf + pr[q]) * vyr[q];
+                    const int yi = pj * TX + (pi - 3);
+                    fpy[yi] = 0.5 * (Gf + ay * uf);
+                    fmy[yi] = 0.5 * (Gf - ay * uf);
+                }
+            }
+        }
+        __syncthreads();
+        for (int r = tid; r < G::NIX; r += WG) {
+            const int lj = r / (TX + 1), k = r - lj * (TX + 1);
+            if (lj < th && k <= tw) {
+                const double* P = fpx + lj * G::PW + k;
+                const double* Mn = fmx + lj * G::PW + k;
+                fhx[r] = weno5(P[0], P[1], P[2], P[3], P[4]) + weno5(Mn[5], Mn[4], Mn[3], Mn[2], Mn[1]);
+            }
+        }
+        if constexpr (G::TWO) {
+            for (int r = tid; r < G::NIY; r += WG) {
+                const int k = r / TX, li = r - k * TX;
+                if (li < tw && k <= th) {
+                    const double* P = fpy + k * TX + li;
+                    const double* Mn = fmy + k * TX + li;
+                    fhy[r] = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX]) +
+                             weno5(Mn[5 * TX], Mn[4 * TX], Mn[3 * TX], Mn[2 * TX], Mn[TX]);
+                }
+            }
+        }
+        __syncthreads();
+        if (own) {
+            double L = -(fhx[olj * (TX + 1) + oli + 1] - fhx[olj * (TX + 1) + oli]) * idx;
+            if constexpr (G::TWO) L -= (fhy[(olj + 1) * TX + oli] - fhy[olj * TX + oli]) * idy;
+            if constexpr (M == ONESTEP) {
+                if (f == 4) L += scell[olj * TX + oli];
+            }
+            const double u0 = a.U0[(size_t)f * a.pool + oc];
+            const double us = a.Uin[(size_t)f * a.pool + oc];
+            const double un = rk_combine(stage, u0, us, L, dt);
+            a.Uout[(size_t)f * a.pool + oc] = un;
+            unew[f] = un;
+        }
+    }
+
+    // ---------------- phase 2: T, checks, maxima for the next stage
+    double sx = 0.0, sy = 0.0, sc = 0.0;
+    if (own) {
+        double T, c, vx, vy;
+        const unsigned st = owner_state<M, NU>(unew, tcell[olj * TX + oli], D, a.mech, T, c, vx, vy);
+        a.Tout[oc] = T;
+        if (st) atomicOr(a.status, st);
+        const bool skip = (stage == 3) && B.fine_child &&
+                          covered_by_finer(a, D, lev, B.i0 + obi, B.j0 + obj);
+        if (a.reduce_out && !st && !skip) {
+            sx = fabs(vx) + c;
+            sy = fabs(vy) + c;
+            sc = sx * idx + (D.twod ? sy * idy : 0.0);
+        }
+    }
+    if (a.reduce_out)
+        publish_max3(a.red, bout, 2 * slot, 2 * slot + 1, 2 * a.red.nunits + B.domain, sx, sy, sc,
+                     scratch);
+}
+
+template <int M, int NU, int TX, int TY, bool HAS1D, bool HAS2D>
+__global__ __launch_bounds__(WG) void stage_kernel(StageArgs a, int first_tile, int owner_launch) {
+    constexpr int L2 = Geom<TX, TY>::LDS, L1 = Geom<WG, 1>::LDS;
+    __shared__ double smem[(L2 > L1) ? L2 : L1];
+    if (blockIdx.x == 0) stage_bookkeeping(a, owner_launch);
+    const Tile tile = a.tiles[first_tile + blockIdx.x];
+    if (HAS1D && tile.kind == 1) {
+        if constexpr (HAS1D) stage_tile<M, NU, WG, 1>(a, tile, smem);
+    } else {
+        if constexpr (HAS2D) stage_tile<M, NU, TX, TY>(a, tile, smem);
+    }
+    if (a.stage == 3 && owner_launch && blockIdx.x == 0) {
+        // t and the step counter are read by the next step's first stage only
+        if (M != DETAILED) step_finish(a);
+    }
+}
+
+// ------------------------------------------------------------------ per-cell kernels
+// Cell of a tile owned by this thread (same mapping as the stage kernel).
+struct CellRef {
+    long long c;
+    int I, J;     // level coordinates
+    bool own;
+};
+
+__device__ __forceinline__ CellRef tile_cell(const StageArgs& a, const Tile& tile, const DevBlock& B) {
+    (void)a;
+    CellRef r;
+    int tw, th, li, lj;
+    if (tile.kind == 1) {
+        li = threadIdx.x;
+        lj = 0;
+        tw = min(WG, B.nx - tile.x0);
+        th = 1;
+    } else {
+        // 2-D tile shapes encode their width in kind >> 8
+        const int TXs = tile.kind >> 8;
+        li = threadIdx.x % TXs;
+        lj = threadIdx.x / TXs;
+        tw = min(TXs, B.nx - tile.x0);
+        th = min(WG / TXs, B.ny - tile.y0);
+    }
+    const int bi = tile.x0 + li, bj = tile.y0 + lj;
+    r.own = (li < tw) && (lj < th) && !ring_at(B, bi, bj);
+    r.c = B.offset + (long long)bj * B.nx + bi;
+    r.I = B.i0 + bi;
+    r.J = B.j0 + bj;
+    return r;
+}
+
+// Call entry: T re-solved from U (warm start = stored T) and the maxima for stage 1.
+template <int M, int NU>
+__global__ __launch_bounds__(WG) void init_kernel(StageArgs a) {
+    __shared__ double scratch[16];
+    const Tile tile = a.tiles[blockIdx.x];
+    const DevBlock B = a.blk[tile.block];
+    const DevDomain& D = a.dom[B.domain];
+    const CellRef r = tile_cell(a, tile, B);
+    const int lev = B.level, slot = D.slot0 + lev;
+    const double idx = (double)(1 << lev) / D.dx0, idy = (double)(1 << lev) / D.dy0;
+    double sx = 0.0, sy = 0.0, sc = 0.0;
+    if (r.own) {
+        double u[NU];
+#pragma unroll
+        for (int f = 0; f < NU; ++f) u[f] = a.Uin[(size_t)f * a.pool + r.c];
+        double T, c, vx, vy;
+        const unsigned st = owner_state<M, NU>(u, a.Tin[r.c], D, a.mech, T, c, vx, vy);
+        a.Tout[r.c] = T;
+        if (st) atomicOr(a.status, st);
+        else {
+            sx = fabs(vx) + c;
+            sy = fabs(vy) + c;
+            sc = sx * idx + (D.twod ? sy * idy : 0.0);
+        }
+    }
+    publish_max3(a.red, 0, 2 * slot, 2 * slot + 1, 2 * a.red.nunits + B.domain, sx, sy, sc, scratch);
+}
+
+// Point-implicit chemistry (Eq. 4.12-4.13) on rho Y_1 .. rho Y_{Ns-1} of each
+// solved cell, then Newton for the new T and the maxima for the next step.
+// X and dq/dX live in LDS (indexed by a wave-uniform species number); the
+// (Ns-1)^2 Jacobian and its LU factorization live in registers.
+template <int NS>
+__device__ __forceinline__ void chem_cell(const DevMech* m, double* Xs, double* dqs, double rho,
+                                          double T, double (&rY)[NS - 1], double dt,
+                                          unsigned& st) {
+    constexpr int NT = NS - 1;
+    const int tid = threadIdx.x;
+    // LDS column per thread: X[0..NS-1], X[NS] = 1 (padding of the molecule lists)
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        Xs[j * WG + tid] = rY[j] * m->invM[j];
+        s += rY[j];
+    }
+    Xs[NT * WG + tid] = (rho - s) * m->invM[NT];
+    Xs[NS * WG + tid] = 1.0;
+    const double lnT = log(T), invT = 1.0 / T;
+    const double lnC = log(PATM / RU) - lnT;      // ln(p_atm / (R_u T))
+    double gt[NS];                                 // h/(R T) - s/R per species
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const double* c = m->nasa[j];
+        gt[j] = c[0] * (1.0 - lnT) - T * (0.5 * c[1] + T * (c[2] * (1.0 / 6.0) +
+                T * (c[3] * (1.0 / 12.0) + T * (c[4] * 0.05)))) + c[5] * invT - c[6];
+    }
+    double w[NT];
+    double J[NT][NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        w[k] = 0.0;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) J[k][q] = 0.0;
+    }
+    for (int i = 0; i < m->nr; ++i) {
+        const double lnkf = m->lnA[i] + m->b[i] * lnT - m->EaR[i] * invT;
+        const double kf = exp(lnkf);
+        double kb = 0.0;
+        if (m->rev[i]) {
+            double sg = 0.0;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) sg += (double)m->dnu[i][j] * gt[j];
+            // K_eq = exp(-sum dnu g) (p_atm/(R_u T))^(sum dnu), Eq. 4.9
+            kb = exp(lnkf + sg - (double)m->dnsum[i] * lnC);
+        }
+        const int f0 = m->lf[i][0], f1 = m->lf[i][1], f2 = m->lf[i][2];
+        const int r0 = m->lb[i][0], r1 = m->lb[i][1], r2 = m->lb[i][2];
+        const double xf0 = Xs[f0 * WG + tid], xf1 = Xs[f1 * WG + tid], xf2 = Xs[f2 * WG + tid];
+        const double xb0 = Xs[r0 * WG + tid], xb1 = Xs[r1 * WG + tid], xb2 = Xs[r2 * WG + tid];
+        const double Rf = kf * (xf0 * xf1 * xf2), Rb = kb * (xb0 * xb1 * xb2);
+        double ctb = 1.0;
+        const bool tbr = m->has_tb[i] != 0;
+        if (tbr) {
+            ctb = 0.0;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) ctb += m->tb[i][j] * Xs[j * WG + tid];
+        }
+        const double net = Rf - Rb;
+        const double q = ctb * net;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) w[k] += m->Mdnu[i][k] * q;
+        // dq/dX_j into LDS (padding slot NS absorbs the entries of missing molecules)
+#pragma unroll
+        for (int j = 0; j <= NS; ++j) dqs[j * WG + tid] = tbr ? m->tb[i][j < NS ? j : 0] * net * (j < NS ? 1.0 : 0.0) : 0.0;
+        dqs[f0 * WG + tid] += ctb * kf * (xf1 * xf2);
+        dqs[f1 * WG + tid] += ctb * kf * (xf0 * xf2);
+        dqs[f2 * WG + tid] += ctb * kf * (xf0 * xf1);
+        dqs[r0 * WG + tid] -= ctb * kb * (xb1 * xb2);
+        dqs[r1 * WG + tid] -= ctb * kb * (xb0 * xb2);
+        dqs[r2 * WG + tid] -= ctb * kb * (xb0 * xb1);
+        // d(rho Y_m): dX_j/d(rho Y_m) = delta_jm / M_m - delta_{j,last} / M_last
+        const double dlast = dqs[NT * WG + tid] * m->invM[NT];
+        double Dm[NT];
+#pragma unroll
+        for (int mm = 0; mm < NT; ++mm) Dm[mm] = dqs[mm * WG + tid] * m->invM[mm] - dlast;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            if (m->dnu[i][k] != 0) {
+                const double ck = m->Mdnu[i][k];
+#pragma unroll
+                for (int mm = 0; mm < NT; ++mm) J[k][mm] += ck * Dm[mm];
+            }
+        }
+    }
+    // (I - dt J) dU = dt w, Gaussian elimination without pivoting
+    double A[NT][NT], bvec[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) A[k][q] = (k == q ? 1.0 : 0.0) - dt * J[k][q];
+        bvec[k] = w[k] * dt;
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+        const double piv = A[c][c];
+        if (!(fabs(piv) > 0.0) || !isfinite(piv)) st |= STB_NONFINITE;
+        const double ip = 1.0 / piv;
+#pragma unroll
+        for (int r = c + 1; r < NT; ++r) {
+            const double fct = A[r][c] * ip;
+#pragma unroll
+            for (int q = c + 1; q < NT; ++q) A[r][q] -= fct * A[c][q];
+            bvec[r] -= fct * bvec[c];
+        }
+    }
+#pragma unroll
+    for (int r = NT - 1; r >= 0; --r) {
+        double sacc = bvec[r];
+#pragma unroll
+        for (int q = r + 1; q < NT; ++q) sacc -= A[r][q] * bvec[q];
+        bvec[r] = sacc / A[r][r];
+    }
+#pragma unroll
+    for (int k = 0; k < NT; ++k) rY[k] += bvec[k];
+}
+
+template <int NS>
+__global__ __launch_bounds__(WG) void chem_kernel(StageArgs a) {
+    constexpr int NU = NS + 3;
+    __shared__ double Xs[(NS + 1) * WG];
+    __shared__ double dqs[(NS + 1) * WG];
+    __shared__ double scratch[16];
+    const Tile tile = a.tiles[blockIdx.x];
+    const DevBlock B = a.blk[tile.block];
+    const DevDomain& D = a.dom[B.domain];
+    const CellRef r = tile_cell(a, tile, B);
+    const int lev = B.level, slot = D.slot0 + lev;
+    const double dt = a.dt[B.domain];
+    const double idx = (double)(1 << lev) / D.dx0, idy = (double)(1 << lev) / D.dy0;
+    if (blockIdx.x == 0) step_finish(a);
+    if (!(dt > 0.0)) return;
+    double sx = 0.0, sy = 0.0, sc = 0.0;
+    double u[NU];
+    double T = 1.0;
+    unsigned st = 0u;
+    if (r.own) {
+#pragma unroll
+        for (int f = 0; f < NU; ++f) u[f] = a.Uout[(size_t)f * a.pool + r.c];
+        T = a.Tout[r.c];
+    } else {
+        // inactive lanes run the same arithmetic on a harmless state
+#pragma unroll
+        for (int f = 0; f < NU; ++f) u[f] = 0.0;
+        u[0] = 1.0;
+    }
+    double rY[NS - 1];
+#pragma unroll
+    for (int k = 0; k < NS - 1; ++k) rY[k] = u[4 + k];
+    chem_cell<NS>(a.mech, Xs, dqs, u[0], T, rY, dt, st);
+    if (r.own) {
+#pragma unroll
+        for (int k = 0; k < NS - 1; ++k) {
+            u[4 + k] = rY[k];
+            a.Uout[(size_t)(4 + k) * a.pool + r.c] = rY[k];
+        }
+        double Tn, c, vx, vy;
+        st |= owner_state<DETAILED, NU>(u, T, D, a.mech, Tn, c, vx, vy);
+        a.Tout[r.c] = Tn;
+        if (st) atomicOr(a.status, st);
+        const bool skip = B.fine_child && covered_by_finer(a, D, lev, r.I, r.J);
+        if (!st && !skip) {
+            sx = fabs(vx) + c;
+            sy = fabs(vy) + c;
+            sc = sx * idx + (D.twod ? sy * idy : 0.0);
+        }
+    }
+    publish_max3(a.red, 0, 2 * slot, 2 * slot + 1, 2 * a.red.nunits + B.domain, sx, sy, sc, scratch);
+}
+
+// Four-to-one restriction (Sec. 3.1.4 coarsening): each coarse cell under a
+// valid block of this level becomes the mean of its four children (ring
+// children count with their effective value, the coarse cell itself); T is
+// re-solved; the coarse cell enters the maxima of the next step.
+template <int M, int NU>
+__global__ __launch_bounds__(WG) void restrict_kernel(StageArgs a, const int* fine_blocks) {
+    __shared__ double scratch[16];
+    const DevBlock B = a.blk[fine_blocks[blockIdx.x]];
+    const DevDomain& D = a.dom[B.domain];
+    const int lev = B.level;
+    const double dt = a.dt[B.domain];
+    if (!(dt > 0.0)) return;
+    const int cw = B.nx / 2, ch = B.ny / 2;
+    const int cslot = D.slot0 + lev - 1;
+    const double idx = (double)(1 << (lev - 1)) / D.dx0, idy = (double)(1 << (lev - 1)) / D.dy0;
+    double sx = 0.0, sy = 0.0, sc = 0.0;
+    for (int cc = threadIdx.x; cc < cw * ch; cc += WG) {
+        const int cj = cc / cw, ci = cc - cj * cw;
+        unsigned fl = 0u;
+        const long long cpar = resolve(a, D, lev - 1, (B.i0 >> 1) + ci, (B.j0 >> 1) + cj, fl);
+        double mean[NU];
+        double ch4[4][NU];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int li = 2 * ci + (q & 1), lj = 2 * cj + (q >> 1);
+            long long s;
+            unsigned f2 = 0u;
+            if (!ring_at(B, li, lj)) s = B.offset + (long long)lj * B.nx + li;
+            else s = resolve(a, D, lev - 1, (B.i0 + li) >> 1, (B.j0 + lj) >> 1, f2);
+            double Tq;
+            fetch<NU>(a, s, f2, a.Uout, a.Tout, ch4[q], Tq);
+        }
+#pragma unroll
+        for (int f = 0; f < NU; ++f) mean[f] = ((ch4[0][f] + ch4[1][f]) + (ch4[2][f] + ch4[3][f])) * 0.25;
+        // all children are read before any coarse value changes: a ring child of this
+        // coarse cell resolves to the cell itself, which only this thread writes
+#pragma unroll
+        for (int f = 0; f < NU; ++f) a.Uout[(size_t)f * a.pool + cpar] = mean[f];
+        double T, c, vx, vy;
+        const unsigned st = owner_state<M, NU>(mean, a.Tout[cpar], D, a.mech, T, c, vx, vy);
+        a.Tout[cpar] = T;
+        if (st) atomicOr(a.status, st);
+        else {
+            sx = fmax(sx, fabs(vx) + c);
+            sy = fmax(sy, fabs(vy) + c);
+            sc = fmax(sc, (fabs(vx) + c) * idx + (D.twod ? (fabs(vy) + c) * idy : 0.0));
+        }
+    }
+    publish_max3(a.red, 0, 2 * cslot, 2 * cslot + 1, 2 * a.red.nunits + B.domain, sx, sy, sc,
+                 scratch);
+}
+
+// Ring cells take the injection (one-to-four) of the coarser level after restriction.
+template <int NU>
+__global__ __launch_bounds__(WG) void ring_fill_kernel(StageArgs a, const int* ring_blocks) {
+    const DevBlock B = a.blk[ring_blocks[blockIdx.x]];
+    const DevDomain& D = a.dom[B.domain];
+    if (!(a.dt[B.domain] > 0.0)) return;
+    for (int q = threadIdx.x; q < B.nx * B.ny; q += WG) {
+        const int lj = q / B.nx, li = q - lj * B.nx;
+        if (!ring_at(B, li, lj)) continue;
+        unsigned fl = 0u;
+        const long long s = resolve(a, D, B.level - 1, (B.i0 + li) >> 1, (B.j0 + lj) >> 1, fl);
+        double u[NU], T;
+        fetch<NU>(a, s, fl, a.Uout, a.Tout, u, T);
+        const long long c = B.offset + (long long)lj * B.nx + li;
+#pragma unroll
+        for (int f = 0; f < NU; ++f) a.Uout[(size_t)f * a.pool + c] = u[f];
+        a.Tout[c] = T;
+    }
+}
+
+__global__ void clear_kernel(unsigned long long* buf, int n) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) buf[q] = 0ull;
+}
+
+__global__ void zero_int_kernel(int* p) {
+    if (threadIdx.x == 0) *p = 0;
+}
+
+// Conserved state from primitives (Eq. 4.2), one thread per cell.
+template <int M, int NU>
+__global__ void prim_to_cons_kernel(const DevMech* mech, double gamma, double R, double Q,
+                                    long long n, const double* W, double* U, double* T,
+                                    long long sin, long long sout) {
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double w[NU];
+#pragma unroll
+    for (int f = 0; f < NU; ++f) w[f] = W[(size_t)f * sin + c];
+    if constexpr (M == DETAILED) {
+        constexpr int NS = NU - 3;
+        const double p = w[0], u = w[1], v = w[2], Tt = w[3];
+        double Y[NS], s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS - 1; ++k) {
+            Y[k] = w[4 + k];
+            s += Y[k];
+        }
+        Y[NS - 1] = 1.0 - s;
+        double Rm = 0.0, e = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const double* a = mech->nasa[k];
+            const double h = Tt * (a[0] + Tt * (0.5 * a[1] + Tt * (a[2] * (1.0 / 3.0) +
+                             Tt * (0.25 * a[3] + Tt * (0.2 * a[4]))))) + a[5];
+            Rm += Y[k] * mech->Rk[k];
+            e += Y[k] * mech->Rk[k] * (h - Tt);
+        }
+        const double rho = p / (Rm * Tt);
+        U[c] = rho;
+        U[(size_t)sout + c] = rho * u;
+        U[(size_t)2 * sout + c] = rho * v;
+        U[(size_t)3 * sout + c] = rho * e + 0.5 * rho * (u * u + v * v);
+#pragma unroll
+        for (int k = 0; k < NS - 1; ++k) U[(size_t)(4 + k) * sout + c] = rho * Y[k];
+        T[c] = Tt;
+    } else {
+        const double rho = w[0], u = w[1], v = w[2], p = w[3];
+        U[c] = rho;
+        U[(size_t)sout + c] = rho * u;
+        U[(size_t)2 * sout + c] = rho * v;
+        double E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v);
+        if constexpr (M == ONESTEP) {
+            E += rho * w[4] * Q;
+            U[(size_t)4 * sout + c] = rho * w[4];
+        }
+        U[(size_t)3 * sout + c] = E;
+        T[c] = p / (rho * R);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+bool model_supported(int model, int ns) {
+    if (model == CPG || model == ONESTEP) return true;
+    return model == DETAILED && (ns == 2 || ns == 9);
+}
+
+hipError_t launch_zero_int(int* p, hipStream_t s) {
+    zero_int_kernel<<<1, 64, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_reduce(const Reduce& r, int which, hipStream_t s) {
+    const int n = (which < 0) ? 3 * r.stride : r.stride;
+    unsigned long long* p = (which < 0) ? r.buf : r.buf + (size_t)which * r.stride;
+    clear_kernel<<<1, WG, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+template <int M, int NU>
+static hipError_t launch_stage_m(int kind_mask, int tile_w, const StageArgs& a, int first,
+                                 int n, int owner, hipStream_t s) {
+    const bool h1 = kind_mask & 2, h2 = kind_mask & 1;
+#define JANC_STAGE(TXv, TYv)                                                                      \
+    do {                                                                                          \
+        if (h1 && h2) stage_kernel<M, NU, TXv, TYv, true, true><<<n, WG, 0, s>>>(a, first, owner);   \
+        else if (h1) stage_kernel<M, NU, TXv, TYv, true, false><<<n, WG, 0, s>>>(a, first, owner);  \
+        else stage_kernel<M, NU, TXv, TYv, false, true><<<n, WG, 0, s>>>(a, first, owner);          \
+    } while (0)
+    if (tile_w == 32) JANC_STAGE(32, 8);
+    else if (tile_w == 64) JANC_STAGE(64, 4);
+    else JANC_STAGE(16, 16);
+#undef JANC_STAGE
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(int model, int ns, int kind_mask, int tile_w, const StageArgs& a,
+                        int first_tile, int ntiles, hipStream_t s) {
+    const int owner = (first_tile == 0) ? 1 : 0;
+    if (ntiles <= 0) return hipSuccess;
+    if (model == CPG) return launch_stage_m<CPG, 4>(kind_mask, tile_w, a, first_tile, ntiles, owner, s);
+    if (model == ONESTEP) return launch_stage_m<ONESTEP, 5>(kind_mask, tile_w, a, first_tile, ntiles, owner, s);
+    if (ns == 9) return launch_stage_m<DETAILED, 12>(kind_mask, tile_w, a, first_tile, ntiles, owner, s);
+    if (ns == 2) return launch_stage_m<DETAILED, 5>(kind_mask, tile_w, a, first_tile, ntiles, owner, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_init(int model, int ns, int tile_w, const StageArgs& a, hipStream_t s) {
+    (void)tile_w;
+    const int n = a.ntiles;
+    if (n <= 0) return hipSuccess;
+    if (model == CPG) init_kernel<CPG, 4><<<n, WG, 0, s>>>(a);
+    else if (model == ONESTEP) init_kernel<ONESTEP, 5><<<n, WG, 0, s>>>(a);
+    else if (ns == 9) init_kernel<DETAILED, 12><<<n, WG, 0, s>>>(a);
+    else if (ns == 2) init_kernel<DETAILED, 5><<<n, WG, 0, s>>>(a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_chem(int model, int ns, int tile_w, const StageArgs& a, hipStream_t s) {
+    (void)tile_w;
+    if (model != DETAILED || a.ntiles <= 0) return hipSuccess;
+    if (ns == 9) chem_kernel<9><<<a.ntiles, WG, 0, s>>>(a);
+    else if (ns == 2) chem_kernel<2><<<a.ntiles, WG, 0, s>>>(a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(int model, int ns, const StageArgs& a, const int* fine_blocks, int nfine,
+                           hipStream_t s) {
+    if (nfine <= 0) return hipSuccess;
+    if (model == CPG) restrict_kernel<CPG, 4><<<nfine, WG, 0, s>>>(a, fine_blocks);
+    else if (model == ONESTEP) restrict_kernel<ONESTEP, 5><<<nfine, WG, 0, s>>>(a, fine_blocks);
+    else if (ns == 9) restrict_kernel<DETAILED, 12><<<nfine, WG, 0, s>>>(a, fine_blocks);
+    else if (ns == 2) restrict_kernel<DETAILED, 5><<<nfine, WG, 0, s>>>(a, fine_blocks);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_ring_fill(int model, int ns, const StageArgs& a, const int* ring_blocks, int nring,
+                            hipStream_t s) {
+    if (nring <= 0) return hipSuccess;
+    const int nu = (model == CPG) ? 4 : (model == ONESTEP) ? 5 : ns + 3;
+    if (nu == 4) ring_fill_kernel<4><<<nring, WG, 0, s>>>(a, ring_blocks);
+    else if (nu == 5) ring_fill_kernel<5><<<nring, WG, 0, s>>>(a, ring_blocks);
+    else if (nu == 12) ring_fill_kernel<12><<<nring, WG, 0, s>>>(a, ring_blocks);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_prim_to_cons(int model, int ns, const DevMech* mech, double gamma, double R,
+                               double Q, long long n, const double* W, double* U, double* T,
+                               long long sin, long long sout, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int nb = (int)((n + WG - 1) / WG);
+    if (model == CPG) prim_to_cons_kernel<CPG, 4><<<nb, WG, 0, s>>>(mech, gamma, R, Q, n, W, U, T, sin, sout);
+    else if (model == ONESTEP) prim_to_cons_kernel<ONESTEP, 5><<<nb, WG, 0, s>>>(mech, gamma, R, Q, n, W, U, T, sin, sout);
+    else if (ns == 9) prim_to_cons_kernel<DETAILED, 12><<<nb, WG, 0, s>>>(mech, gamma, R, Q, n, W, U, T, sin, sout);
+    else if (ns == 2) prim_to_cons_kernel<DETAILED, 5><<<nb, WG, 0, s>>>(mech, gamma, R, Q, n, W, U, T, sin, sout);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace janc

@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every entry point include/janc.h declares
+(no compute calls: no GPU here)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "janc.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(janc_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["janc_create", "janc_destroy", "janc_step", "janc_step_blocks", "janc_adjoint",
+              "janc_plan_create", "janc_init_state", "janc_sync_status"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2504_13750_amd as janc
+    lib = janc.load()
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_header():
+    from paper_2504_13750_amd import _lib as L
+    assert ctypes.sizeof(L.janc_block) == 40
+    assert ctypes.sizeof(L.janc_physics) == 40
+    assert ctypes.sizeof(L.janc_time) == 24
+    assert ctypes.sizeof(L.janc_grid) == 8 + 16 + 16 + 4 * 16 * 8
+    assert ctypes.sizeof(L.janc_mech) == 8 + 10 * 8
+
+
+def test_block_dtype_matches_cases():
+    import numpy as np
+    import paper_2504_13750_amd as janc
+    from cases.common import BLOCK_DTYPE
+    assert janc.BLOCK_DTYPE == BLOCK_DTYPE
+    assert janc.BLOCK_DTYPE.itemsize == 40
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    from paper_2504_13750_amd import _lib as L
+    monkeypatch.setattr(L, "_LIB", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(L.LibraryMissing):
+        L.lib()

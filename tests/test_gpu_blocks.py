@@ -1,0 +1,125 @@
+"""GPU parity on block tables (AMR hierarchies and ensembles) against the oracle,
+and the invariances of the batched launch.
+
+Bar: max relative error per conserved field <= 1e-10 after N steps; the batched
+and per-block launch forms and block splits of a uniform grid are bitwise equal.
+The coarse-fine coupling (ring cells, restriction) has no closed form: its
+parity is against the oracle only ("parity unpinned" beyond the oracle's own
+restriction, full-refinement and constant-state pins).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2504_13750_amd as janc
+from cases import (detonation_tube_case, ensemble_case, amr_case, synthetic_mechanism, Domain,
+                   BlockCase, MODEL_ONESTEP, MODEL_DETAILED, BC_ZEROGRAD, BC_SLIPWALL)
+from cases.common import make_blocks
+from cases.amr import build_hierarchy, front_primitives
+from gpu_util import run_blocks, run_uniform, rel_err
+from test_oracle_blocks import _split_uniform, _gather, _small_amr
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _cmp_blocks(bcase, nsteps, tol=TOL, **kw):
+    Ug, Tg, tg = run_blocks(bcase, nsteps, **kw)
+    Uo, To = oracle.block_state(bcase)
+    Uo, To, to, _, _ = oracle.step_blocks(bcase, Uo, To, nsteps)
+    valid = np.zeros(bcase.pool_cells, bool)
+    for b in bcase.blocks[bcase.blocks["valid"] != 0]:
+        valid[b["offset"]:b["offset"] + b["nx"] * b["ny"]] = True
+    e = rel_err(Ug[:, valid], Uo[:, valid])
+    eT = rel_err(Tg[None, valid], To[None, valid])[0]
+    print(f"  {bcase.name}: per-field rel err {np.array2string(e, precision=2)}, T {eT:.2e}",
+          flush=True)
+    assert np.all(e <= tol), e
+    assert eT <= tol
+    assert np.allclose(tg, to, rtol=1e-12, atol=0)
+    return Ug, Uo
+
+
+def test_block_split_equals_uniform_bitwise():
+    c = detonation_tube_case(nx=128, ny=32, seed=17)
+    bc, recs = _split_uniform(c, [0, 24, 64, 72, 128], [0, 8, 24, 32])
+    Uu, _, tu, _ = run_uniform(c, 40)
+    Ub, _, tb = run_blocks(bc, 40)
+    assert tb[0] == tu
+    assert np.array_equal(_gather(Ub, recs, Uu.shape), Uu)
+
+
+def test_block_split_vs_oracle():
+    c = detonation_tube_case(nx=128, ny=32, seed=17)
+    bc, _ = _split_uniform(c, [0, 24, 64, 72, 128], [0, 8, 24, 32])
+    _cmp_blocks(bc, 60)
+
+
+def test_per_block_launches_equal_batched_bitwise():
+    bc = _small_amr()
+    Ua, Ta, ta = run_blocks(bc, 6)
+    Ub, Tb, tb = run_blocks(bc, 6, flags=janc.PLAN_PER_BLOCK)
+    assert np.array_equal(Ua, Ub) and np.array_equal(ta, tb)
+
+
+@pytest.mark.parametrize("tile", [16, 32, 64])
+def test_tile_shapes_agree(tile):
+    bc = _small_amr()
+    Ua, _, _ = run_blocks(bc, 4, tile=16)
+    Ub, _, _ = run_blocks(bc, 4, tile=tile)
+    assert np.array_equal(Ua, Ub)
+
+
+def test_amr_onestep_three_levels_vs_oracle():
+    _cmp_blocks(_small_amr(), 20)
+
+
+def test_graph_and_direct_launch_agree():
+    bc = _small_amr()
+    Ua, _, _ = run_blocks(bc, 5)
+    Ub, _, _ = run_blocks(bc, 5, flags=janc.PLAN_NO_GRAPH)
+    assert np.array_equal(Ua, Ub)
+
+
+def test_ensemble_vs_oracle():
+    e = ensemble_case(n1d=6, n2d=4, seed=77)
+    _cmp_blocks(e, 25)
+
+
+def test_ensemble_instance_equals_alone_bitwise():
+    e = ensemble_case(n1d=3, n2d=3, seed=78)
+    Ua, _, ta = run_blocks(e, 12)
+    for d in range(len(e.domains)):
+        b = e.blocks[d]
+        s = slice(int(b["offset"]), int(b["offset"] + b["nx"] * b["ny"]))
+        sub = BlockCase(name=f"inst{d}", model=e.model, domains=[e.domains[d]],
+                        blocks=make_blocks([(0, 0, 0, 0, int(b["nx"]), int(b["ny"]))]),
+                        W=e.W[:, s], cfl=e.cfl)
+        U1, _, t1 = run_blocks(sub, 12)
+        assert np.array_equal(U1, Ua[:, s]) and t1[0] == ta[d]
+
+
+def _small_detailed_amr(nx0=128, ny0=64, nlevels=3):
+    mech = synthetic_mechanism()
+    c = amr_case(mech=mech, nx0=nx0, ny0=ny0, dx0=25e-6 * 1024 / nx0 / 4, nlevels=nlevels,
+                 widths=(0.28e-3, 0.2e-3), blk0=32, nsteps=3)
+    return c
+
+
+def test_amr_detailed_vs_oracle():
+    c = _small_detailed_amr()
+    assert len(c.blocks) > 20
+    _cmp_blocks(c, 3)
+
+
+def test_bad_table_rejected():
+    c = detonation_tube_case(nx=64, ny=16, seed=3)
+    bc, _ = _split_uniform(c, [0, 32, 64], [0, 16])
+    bc.blocks = bc.blocks.copy()
+    bc.blocks[1]["i0"] = 24              # overlaps block 0 and leaves a gap
+    ctx = janc.Context(janc.ONESTEP)
+    with pytest.raises(janc.JancError) as ei:
+        ctx.plan(janc.domains_of(bc), bc.blocks, bc.pool_cells)
+    assert ei.value.code == -1
+    ctx.close()

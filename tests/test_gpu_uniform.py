@@ -1,0 +1,138 @@
+"""GPU parity on uniform grids: the HIP path (through the C ABI) against the CPU
+oracle on the same seeded inputs.
+
+Bar: max relative error per conserved field <= 1e-10 (field-max normalization),
+temperatures likewise; time steps to 1e-12. Sizes span several tiles and
+ragged tails; the full 1024 x 128 detonation tube runs in the launch
+configuration the benchmark times.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from cases import (sod_case, detonation_tube_case, Case, MODEL_CPG, MODEL_ONESTEP, BC_PERIODIC,
+                   BC_ZEROGRAD, BC_SLIPWALL, BC_DIRICHLET, synthetic_mechanism)
+from cases.amr import detailed_front_case
+from gpu_util import run_uniform, rel_err, context_for, torch_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _compare(case, nsteps, tol=TOL, **kw):
+    Ug, Tg, tg, dg = run_uniform(case, nsteps, **kw)
+    Uo, To = oracle.case_state(case)
+    okw = {k: v for k, v in kw.items() if k in ("dt_fixed", "t_end", "cfl")}
+    Uo, To, to, do, _ = oracle.step(case, Uo, To, nsteps, **okw)
+    e = rel_err(Ug, Uo)
+    eT = rel_err(Tg[None], To[None])[0]
+    print(f"  {case.name}: per-field rel err {np.array2string(e, precision=2)}, T {eT:.2e}, "
+          f"t gpu {tg:.12e} oracle {to:.12e}", flush=True)
+    assert np.all(e <= tol), e
+    assert eT <= tol
+    assert tg == pytest.approx(to, rel=1e-12)
+    assert np.allclose(dg, do, rtol=1e-12, atol=0.0)
+    return Ug, Uo
+
+
+@pytest.mark.parametrize("model", ["cpg", "onestep", "detailed"])
+def test_init_state_parity(model):
+    torch, dev = torch_dev()
+    if model == "cpg":
+        c = sod_case(nx=64)
+    elif model == "onestep":
+        c = detonation_tube_case(nx=40, ny=8, seed=3)
+    else:
+        c = detailed_front_case(nx=24, ny=8)
+    ctx = context_for(c)
+    import paper_2504_13750_amd as janc
+    U, T = ctx.init_state(janc.physics_of(c), torch.tensor(c.W, dtype=torch.float64, device=dev))
+    Uo, To = oracle.case_state(c)
+    assert np.all(rel_err(U.cpu().numpy(), Uo) <= 1e-14)
+    assert np.all(rel_err(T.cpu().numpy()[None], To[None]) <= 1e-14)
+    ctx.close()
+
+
+def test_sod_full_run():
+    """Config 1: 400 cells, CFL 0.5 to t = 0.2 (last step clipped, later steps no-ops)."""
+    c = sod_case()
+    _compare(c, 400)
+
+
+def test_detonation_ragged_tiles():
+    # 100 x 20: neither 16 nor 32 divides the grid, so tiles have ragged tails
+    _compare(detonation_tube_case(nx=100, ny=20, seed=21), 120)
+
+
+def test_detonation_many_steps_small():
+    _compare(detonation_tube_case(nx=128, ny=32, seed=22), 400)
+
+
+def test_detonation_config2_full_size():
+    """1024 x 128 tube (the benchmark's uniform workload) for 60 steps."""
+    _compare(detonation_tube_case(), 60)
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (5, 1), (3, 1), (17, 9), (256, 1), (700, 1)])
+def test_small_and_one_dimensional_grids(shape):
+    nx, ny = shape
+    rng = np.random.default_rng(nx * 31 + ny)
+    W = np.zeros((5, ny, nx))
+    W[0] = 1.0 + 0.2 * rng.uniform(size=(ny, nx))
+    W[1] = 0.3 * rng.normal(size=(ny, nx))
+    W[2] = 0.0 if ny == 1 else 0.3 * rng.normal(size=(ny, nx))
+    W[3] = 1.0 + rng.uniform(size=(ny, nx))
+    W[4] = rng.uniform(size=(ny, nx))
+    c = Case(name=f"rand{nx}x{ny}", model=MODEL_ONESTEP, nx=nx, ny=ny, dx=0.05, dy=0.07,
+             bc=[BC_PERIODIC, BC_PERIODIC, BC_SLIPWALL, BC_SLIPWALL], W=W, gamma=1.25, R=1.0,
+             Q=3.0, Ea=4.0, k=2.0, cfl=0.45)
+    _compare(c, 30)
+
+
+@pytest.mark.parametrize("bc", [(BC_ZEROGRAD, BC_ZEROGRAD, BC_ZEROGRAD, BC_ZEROGRAD),
+                                (BC_SLIPWALL, BC_DIRICHLET, BC_PERIODIC, BC_PERIODIC),
+                                (BC_DIRICHLET, BC_SLIPWALL, BC_DIRICHLET, BC_ZEROGRAD)])
+def test_boundary_kinds(bc):
+    c = detonation_tube_case(nx=48, ny=24, seed=5)
+    c.bc = list(bc)
+    st = np.array([1.1, 0.2, -0.1, 1.3, 0.9])
+    c.bc_prim = [st if b == BC_DIRICHLET else None for b in bc]
+    _compare(c, 40)
+
+
+def test_cpg_two_dimensional_fixed_dt():
+    rng = np.random.default_rng(12)
+    nx, ny = 64, 48
+    W = np.zeros((4, ny, nx))
+    W[0] = 1.0 + 0.5 * (rng.uniform(size=(ny, nx)) > 0.5)
+    W[1] = 0.1 * rng.normal(size=(ny, nx))
+    W[2] = 0.1 * rng.normal(size=(ny, nx))
+    W[3] = 1.0 + (rng.uniform(size=(ny, nx)) > 0.7)
+    c = Case(name="cpg2d", model=MODEL_CPG, nx=nx, ny=ny, dx=0.01, dy=0.01,
+             bc=[BC_SLIPWALL, BC_ZEROGRAD, BC_PERIODIC, BC_PERIODIC], W=W, gamma=1.4, R=287.0)
+    _compare(c, 50, dt_fixed=1e-3)
+
+
+def test_detailed_front_uniform():
+    """9-species front (NASA-7 Newton + point-implicit chemistry) on a uniform grid."""
+    c = detailed_front_case(nx=48, ny=40)
+    _compare(c, 4)
+
+
+def test_zero_steps_only_resolves_temperature():
+    c = detailed_front_case(nx=32, ny=16)
+    Ug, Tg, tg, _ = run_uniform(c, 0)
+    Uo, To = oracle.case_state(c)
+    assert np.array_equal(Ug, Uo) or np.all(rel_err(Ug, Uo) <= 1e-15)
+    assert tg == 0.0
+
+
+def test_status_flag_on_negative_density():
+    """A state with negative pressure is reported through the sticky status word."""
+    import paper_2504_13750_amd as janc
+    c = detonation_tube_case(nx=32, ny=8, seed=1)
+    c.W[3, 4, 10] = -5.0           # negative pressure in one cell
+    with pytest.raises(janc.JancError) as ei:
+        run_uniform(c, 1)
+    assert ei.value.code == -6
