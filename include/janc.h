@@ -176,6 +176,16 @@ janc_status janc_step_blocks(janc_ctx *ctx, janc_plan *plan, const janc_time *ti
                              double *U_pool, double *T_pool, int nsteps, double *t,
                              void *stream);
 
+/* Profiling aid: one step of a plan (as in janc_step_blocks, after the call-entry
+ * temperature solve) launched without graph capture, with HIP events recorded on
+ * `stream` around each launch group. ms (host) [6] receives the durations in
+ * milliseconds of RK stage 1, stage 2, stage 3, the chemistry step, the
+ * restriction (all levels) and the ring refill. U_pool, T_pool and t advance by
+ * the step. Synchronizes the stream. */
+janc_status janc_profile_step(janc_ctx *ctx, janc_plan *plan, const janc_time *time,
+                              double *U_pool, double *T_pool, double *t, double *ms,
+                              void *stream);
+
 /* ------------------------------------------------------------------ adjoint */
 /* Discrete adjoint (the exact gradient of the discrete map) of nsteps steps of
  * janc_step for the one-step model with a fixed dt (time->dt_fixed > 0), in the

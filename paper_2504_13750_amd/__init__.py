@@ -218,6 +218,17 @@ class Context:
                                              _dptr(t, plan.ndom, "t"),
                                              C.c_void_p(_stream_handle(stream))))
 
+    def profile_step(self, plan, time, U, T, t, stream=None):
+        """One step with HIP events around each launch group; returns milliseconds of
+        [stage 1, stage 2, stage 3, chemistry, restriction, ring refill]."""
+        ms = (C.c_double * 6)()
+        self._check(L.lib().janc_profile_step(self.h, plan.h, C.byref(time),
+                                              _dptr(U, self.nfields * plan.pool_cells, "U"),
+                                              _dptr(T, plan.pool_cells, "T"),
+                                              _dptr(t, plan.ndom, "t"), ms,
+                                              C.c_void_p(_stream_handle(stream))))
+        return [ms[q] for q in range(6)]
+
     def adjoint(self, grid, phys, time, W0, nsteps, ckpt_every, probe_cell, probe_w,
                 stream=None):
         """Returns (loss, dL/dW0, dL/dtheta) as device tensors ([1], [5, ny, nx], [2])."""

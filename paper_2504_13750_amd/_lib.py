@@ -60,6 +60,8 @@ EXPORTS = {
     "janc_plan_destroy": (None, [VP]),
     "janc_plan_set_tile": (I, [VP, I]),
     "janc_step_blocks": (I, [VP, VP, C.POINTER(janc_time), VP, VP, I, VP, VP]),
+    "janc_profile_step": (I, [VP, VP, C.POINTER(janc_time), VP, VP, VP, C.POINTER(C.c_double),
+                              VP]),
     "janc_adjoint": (I, [VP, C.POINTER(janc_grid), C.POINTER(janc_physics), C.POINTER(janc_time),
                          VP, I, I, I, PI, PD, VP, VP, VP, VP]),
 }

@@ -677,6 +677,69 @@ janc_status janc_step(janc_ctx* c, const janc_grid* g, const janc_physics* ph, c
     return run_steps(c, c->uplan, tm, U, T, nsteps, t, dt_log, (hipStream_t)stream);
 }
 
+janc_status janc_profile_step(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U,
+                              double* T, double* t, double* ms, void* stream) {
+    if (!c || !P || !tm || !U || !T || !t || !ms) return fail(c, JANC_EINVAL, "bad arguments");
+    if (P->ctx != c) return fail(c, JANC_EINVAL, "plan belongs to another context");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    const StageArgs base = base_args(P, tm, U, T, t, nullptr, 0);
+    HIPCHK(c, launch_clear_reduce(base.red, -1, s), "clear launch");
+    HIPCHK(c, launch_zero_int(P->dstep, s), "counter launch");
+    StageArgs a0 = base;
+    a0.Uin = U;
+    a0.Tin = T;
+    a0.Tout = T;
+    HIPCHK(c, launch_init(c->model, c->ns, P->tile_w, a0, s), "init launch");
+    hipEvent_t ev[7];
+    for (int q = 0; q < 7; ++q) HIPCHK(c, hipEventCreate(&ev[q]), "hipEventCreate");
+    const int model = c->model, ns = c->ns;
+    double* Uin[3] = {U, P->U1, P->U2};
+    double* Uout[3] = {P->U1, P->U2, U};
+    double* Tin[3] = {T, P->T1, P->T2};
+    double* Tout[3] = {P->T1, P->T2, T};
+    hipError_t e = hipEventRecord(ev[0], s);
+    for (int st = 1; st <= 3 && e == hipSuccess; ++st) {
+        StageArgs a = base;
+        a.stage = st;
+        a.Uin = Uin[st - 1];
+        a.Uout = Uout[st - 1];
+        a.Tin = Tin[st - 1];
+        a.Tout = Tout[st - 1];
+        a.reduce_out = (st == 3 && model == DETAILED) ? 0 : 1;
+        if (P->flags & JANC_PLAN_PER_BLOCK) {
+            for (int id = 0; id < P->nblk && e == hipSuccess; ++id)
+                e = launch_stage(model, ns, P->kind_mask, P->tile_w, a, P->tile_first[id], P->tile_count[id], s);
+        } else {
+            e = launch_stage(model, ns, P->kind_mask, P->tile_w, a, 0, a.ntiles, s);
+        }
+        if (e == hipSuccess) e = hipEventRecord(ev[st], s);
+    }
+    StageArgs a = base;
+    a.stage = 3;
+    a.Uin = U;
+    a.Uout = U;
+    a.Tin = T;
+    a.Tout = T;
+    if (e == hipSuccess && model == DETAILED) e = launch_chem(model, ns, P->tile_w, a, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[4], s);
+    for (int l = P->maxlev; l >= 1 && e == hipSuccess; --l)
+        e = launch_restrict(model, ns, a, P->dfine + P->fine_off[l], (int)P->fine[l].size(), s);
+    if (e == hipSuccess) e = hipEventRecord(ev[5], s);
+    if (e == hipSuccess && !P->ring_blocks.empty())
+        e = launch_ring_fill(model, ns, a, P->dring, (int)P->ring_blocks.size(), s);
+    if (e == hipSuccess) e = hipEventRecord(ev[6], s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[6]);
+    for (int q = 0; q < 6 && e == hipSuccess; ++q) {
+        float f = 0.0f;
+        e = hipEventElapsedTime(&f, ev[q], ev[q + 1]);
+        ms[q] = f;
+    }
+    for (int q = 0; q < 7; ++q) hipEventDestroy(ev[q]);
+    if (e != hipSuccess) return hipfail(c, e, "profile step");
+    return JANC_OK;
+}
+
 janc_status janc_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
                          const janc_time* tm, const double* W0, int nsteps, int ckpt_every,
                          int nprobes, const int* probe_cell, const double* probe_w, double* loss,
