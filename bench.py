@@ -94,6 +94,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-block", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
@@ -171,14 +172,9 @@ def main():
         ring_ms.append(ms[5])
     ctx.sync_status()
     stage_avg = sum(stage_ms) / len(stage_ms)
-    ring = np.zeros(case.pool_cells, bool)
-    solved = 0
-    try:
-        import oracle
-        ring = oracle.ring_flags(case) == 1
-    except Exception:
-        pass
-    ring_cells = int(ring.sum())
+    pst = plan.stats()
+    ring_cells = int(pst["ring_cells"])
+    assert pst["cells"] == cells
     solved = cells - ring_cells
     flops = stage_flops(2, nU, True) * solved
     achieved_tf = flops / (stage_avg * 1e-3) / 1e12
@@ -203,6 +199,51 @@ def main():
         log(f"[bench] per-block form {per_block['ms_per_step']:.3f} ms/step "
             f"-> fused speed-up {value / pb_value:.2f}x")
         pplan.close()
+
+    # ------------------------------------------------------------ adjoint / forward cost
+    adjoint = None
+    if not args.no_adjoint:
+        from cases import adjoint_case
+        a = adjoint_case()
+        ac = a["case"]
+        actx = janc.Context(janc.ONESTEP)
+        aph = janc.physics_of(ac)
+        ag = janc.grid_of(ac)
+        atm = janc.make_time(0.0, ac.dt_fixed, 0.0)
+        W0 = torch.tensor(ac.W, dtype=torch.float64, device=dev)
+
+        def fwd():
+            U0, T0 = actx.init_state(aph, W0)
+            t0 = torch.zeros(1, dtype=torch.float64, device=dev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            actx.step(ag, aph, atm, U0, T0, ac.nsteps, t0)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / 1e3
+
+        def adj():
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            out = actx.adjoint(ag, aph, atm, W0, ac.nsteps, a["ckpt_every"], a["probe_cell"],
+                               a["probe_w"])
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / 1e3, out
+
+        fwd()
+        adj()                      # warm-up (workspace, graph capture)
+        tf = min(fwd() for _ in range(3))
+        ta = min(adj()[0] for _ in range(3))
+        actx.sync_status()
+        adjoint = {"workload": f"one-step tube {ac.nx}x{ac.ny}, {ac.nsteps} steps, "
+                               f"checkpoints every {a['ckpt_every']}",
+                   "forward_s": tf, "adjoint_s": ta, "adjoint_over_forward": ta / tf}
+        log(f"[bench] adjoint {ta * 1e3:.2f} ms vs forward {tf * 1e3:.2f} ms: "
+            f"{ta / tf:.2f}x")
+        actx.close()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -247,6 +288,7 @@ def main():
         "kernels_ms": {"stage": stage_avg, "chemistry": float(np.mean(chem_ms)),
                        "restriction": float(np.mean(restr_ms)), "ring": float(np.mean(ring_ms))},
         "per_block": per_block,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
         "context": "paper (A100, real H2-O2 mechanism, 2.76 M cells incl. invalid blocks): "
                    "0.18 s/step synchronous AMR, about 4.6e7 cell-stage/s; not the same "

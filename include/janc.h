@@ -162,6 +162,11 @@ janc_status janc_plan_create(janc_ctx *ctx, int ndomains, const janc_domain *dom
                              int flags, janc_plan **out);
 void janc_plan_destroy(janc_plan *plan);
 
+/* Plan statistics (host) out[4]: cells of valid blocks, coarse-fine ring cells
+ * among them (not solved; they hold the coarser level's value), valid blocks,
+ * and tiles of one stage launch. */
+janc_status janc_plan_stats(const janc_plan *plan, long long *out);
+
 /* Per-plan tile shape (autotuner hook): 0 = automatic, else tile width in cells
  * for 2-D blocks (16 or 32 or 64; height = 256 / width). Synchronous. */
 janc_status janc_plan_set_tile(janc_plan *plan, int tile_width);

@@ -133,6 +133,12 @@ class Plan:
     def set_tile(self, width):
         self.ctx._check(L.lib().janc_plan_set_tile(self.h, int(width)))
 
+    def stats(self):
+        """dict(cells, ring_cells, blocks, tiles) of the plan."""
+        out = (C.c_longlong * 4)()
+        self.ctx._check(L.lib().janc_plan_stats(self.h, out))
+        return {"cells": out[0], "ring_cells": out[1], "blocks": out[2], "tiles": out[3]}
+
     def close(self):
         if self.h:
             L.lib().janc_plan_destroy(self.h)

@@ -30,6 +30,11 @@ struct janc_ctx {
     janc_plan* uplan = nullptr;
     janc_grid ugrid{};
     janc_physics uphys{};
+    // adjoint workspace (grown on demand)
+    std::vector<void*> adj_bufs;
+    size_t adj_key = 0;
+    double* adj_mem = nullptr;
+    size_t adj_doubles = 0;
 };
 
 struct GraphKey {
@@ -59,6 +64,7 @@ struct janc_plan {
     std::vector<std::vector<int>> fine;        // per level >= 1: valid block ids
     std::vector<int> ring_blocks;
     std::vector<double> hdir;
+    long long cells = 0, ring_cells = 0;
     // device
     DevDomain* ddom = nullptr;
     DevBlock* dblk = nullptr;
@@ -351,7 +357,11 @@ janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, con
                     return fail(c, JANC_EINVAL, "refined block at (%d,%d) level %d covers coarse-fine ring cells of level %d", h.i0, h.j0, h.level, h.level - 1);
             }
         P->fine[h.level].push_back(id);
-        if (h.ring[0] | h.ring[1] | h.ring[2] | h.ring[3]) P->ring_blocks.push_back(id);
+        if (h.ring[0] | h.ring[1] | h.ring[2] | h.ring[3]) {
+            P->ring_blocks.push_back(id);
+            for (int lj = 0; lj < h.ny; ++lj)
+                for (int li = 0; li < h.nx; ++li) P->ring_cells += ring_cell(h, li, lj) ? 1 : 0;
+        }
     }
     // ---- Dirichlet rows (conserved state + T), converted on the device
     P->hdir.assign((size_t)std::max(ndir, 1) * (MAXF + 1), 0.0);
@@ -379,6 +389,7 @@ janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, con
     }
     P->ndom = nd;
     P->nblk = (int)P->hblk.size();
+    for (const auto& h : P->hblk) P->cells += (long long)h.nx * h.ny;
     // ---- device tables and workspaces
     if ((st = upload(c, &P->ddom, P->hdom))) return st;
     if ((st = upload(c, &P->dblk, P->hblk))) return st;
@@ -568,6 +579,191 @@ janc_status uniform_plan(janc_ctx* c, const janc_grid* g, const janc_physics* ph
     return JANC_OK;
 }
 
+
+// ---------------------------------------------------------------- discrete adjoint
+// Forward with checkpoints every k steps (and the probe loss), then segments in
+// reverse: recompute the segment from its checkpoint storing every stage input,
+// and sweep its steps backwards through the three stage adjoints.
+janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
+                        const janc_time* tm, const double* W0, int N, int K, int np,
+                        const int* pc, const double* pw, double* loss, double* gW,
+                        double* theta, hipStream_t s) {
+    if (c->model != ONESTEP) return fail(c, JANC_EINVAL, "the adjoint covers the one-step model");
+    if (!(tm->dt_fixed > 0.0)) return fail(c, JANC_EINVAL, "the adjoint needs a fixed dt (dt_fixed > 0)");
+    if (tm->t_end > 0.0) return fail(c, JANC_EINVAL, "the adjoint does not clip to t_end");
+    if (g->nx < 3 || (g->ny != 1 && g->ny < 3))
+        return fail(c, JANC_EINVAL, "adjoint grid needs nx >= 3 and ny = 1 or ny >= 3");
+    const long long n = (long long)g->nx * g->ny;
+    if (n > (1ll << 31) - 1) return fail(c, JANC_EINVAL, "grid too large for the adjoint");
+    for (int q = 0; q < np; ++q)
+        if (pc[q] < 0 || pc[q] >= n) return fail(c, JANC_EINVAL, "probe cell %d out of range", q);
+    janc_status st = uniform_plan(c, g, ph);
+    if (st) return st;
+    janc_plan* P = c->uplan;
+    HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    const int nseg = (N + K - 1) / K;
+    AdjGrid ag{};
+    ag.nx = g->nx;
+    ag.ny = g->ny;
+    ag.twod = g->ny > 1 ? 1 : 0;
+    for (int q = 0; q < 4; ++q) {
+        ag.bc[q] = g->bc[q];
+        ag.dir[q] = P->hdom[0].dir[q];
+    }
+    ag.idx = 1.0 / g->dx;
+    ag.idy = 1.0 / g->dy;
+    ag.gamma = ph->gamma;
+    ag.R = ph->R;
+    ag.Q = ph->Q;
+    ag.Ea = ph->Ea;
+    ag.k = ph->k;
+    ag.dirU = P->ddir;
+    int nbc = 0, nbd = 0;
+    const int nparts = adj_partial_blocks(ag, n, &nbc, &nbd);
+    const long long nxs = (long long)(g->nx + 6) * g->ny;
+    const long long nys = ag.twod ? (long long)g->nx * (g->ny + 6) : 0;
+    const long long nix = (long long)(g->nx + 1) * g->ny;
+    const long long niy = ag.twod ? (long long)g->nx * (g->ny + 1) : 0;
+    const long long n5 = 5 * n;
+    // workspace layout (doubles)
+    struct Seg { size_t off, len; };
+    size_t tot = 0;
+    auto take = [&](size_t len) { Seg r{tot, len}; tot += (len + 31) & ~(size_t)31; return r; };
+    const Seg sCk = take((size_t)nseg * n5), sS0 = take((size_t)(K + 1) * n5), sS1 = take((size_t)K * n5),
+              sS2 = take((size_t)K * n5), sLam = take(n5), sLA = take(n5), sLB = take(n5), sAcc = take(n5),
+              sT0 = take(n), sT1 = take(n), sVx = take(5 * nxs), sFpx = take(5 * nxs), sFmx = take(5 * nxs),
+              sGx = take(5 * nxs), sVy = take(5 * nys), sFpy = take(5 * nys), sFmy = take(5 * nys),
+              sGy = take(5 * nys), sSx = take(nxs), sSy = take(nys), sCx = take(50 * nix),
+              sCy = take(50 * niy), sPart = take(4 * (size_t)std::max(nparts, (int)((n + 255) / 256)) + 8),
+              sMisc = take(16), sPc = take(np + 1), sPw = take(np + 1);
+    if (tot > c->adj_doubles) {
+        if (c->adj_mem) hipFree(c->adj_mem);
+        c->adj_mem = nullptr;
+        c->adj_doubles = 0;
+        if ((st = dalloc(c, &c->adj_mem, tot))) return st;
+        c->adj_doubles = tot;
+    }
+    double* M = c->adj_mem;
+    auto at = [&](const Seg& q) { return M + q.off; };
+    double* ck = at(sCk);
+    double* S0 = at(sS0);
+    double* S1 = at(sS1);
+    double* S2 = at(sS2);
+    double* lam = at(sLam);
+    double* lA = at(sLA);
+    double* lB = at(sLB);
+    double* acc = at(sAcc);
+    double* T0 = at(sT0);
+    double* T1 = at(sT1);
+    double* misc = at(sMisc);
+    int* dpc = (int*)at(sPc);
+    double* dpw = at(sPw);
+    if (np > 0) {
+        HIPCHK(c, hipMemcpyAsync(dpc, pc, sizeof(int) * np, hipMemcpyHostToDevice, s), "probe copy");
+        HIPCHK(c, hipMemcpyAsync(dpw, pw, sizeof(double) * np, hipMemcpyHostToDevice, s), "probe copy");
+    }
+    HIPCHK(c, hipMemsetAsync(loss, 0, sizeof(double), s), "memset");
+    HIPCHK(c, hipMemsetAsync(theta, 0, 2 * sizeof(double), s), "memset");
+    HIPCHK(c, hipMemsetAsync(lam, 0, sizeof(double) * n5, s), "memset");
+    // U0 from the primitives (the Q dependence of E0 is chained at the end)
+    HIPCHK(c, launch_prim_to_cons(ONESTEP, 0, nullptr, ph->gamma, ph->R, ph->Q, n, W0, ck, T0, n, n, s),
+           "init_state");
+    double* tdev = misc;   // forward time (unused by fixed dt), misc[1..] scratch
+    const StageArgs base = base_args(P, tm, ck, T0, tdev, nullptr, 0);
+    auto entry = [&](double* U) -> hipError_t {
+        hipError_t e = launch_clear_reduce(base.red, -1, s);
+        if (e == hipSuccess) e = launch_zero_int(P->dstep, s);
+        StageArgs a0 = base;
+        a0.Uin = U;
+        a0.Tin = T0;
+        a0.Tout = T0;
+        if (e == hipSuccess) e = launch_init(ONESTEP, 0, P->tile_w, a0, s);
+        return e;
+    };
+    auto stage = [&](int stn, double* Un, double* Uin, double* Uout) -> hipError_t {
+        StageArgs a = base;
+        a.stage = stn;
+        a.U0 = Un;
+        a.Uin = Uin;
+        a.Uout = Uout;
+        a.Tin = (stn == 2) ? T1 : T0;
+        a.Tout = (stn == 2) ? T0 : T1;
+        if (stn == 3) { a.Tin = T0; a.Tout = T1; }
+        if (stn == 1) { a.Tin = T1; a.Tout = T0; }
+        a.reduce_out = 1;
+        return launch_stage(ONESTEP, 0, P->kind_mask, P->tile_w, a, 0, a.ntiles, s);
+    };
+    const double dt = tm->dt_fixed;
+    // ---- forward pass with checkpoints and the probe loss
+    HIPCHK(c, entry(ck), "adjoint forward entry");
+    HIPCHK(c, hipMemcpyAsync(T1, T0, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy");
+    double* cur = ck;
+    for (int step = 0; step < N; ++step) {
+        double* nxt = (step + 1 < N && (step + 1) % K == 0) ? ck + (size_t)((step + 1) / K) * n5
+                                                           : ((cur == S0) ? S0 + n5 : S0);
+        HIPCHK(c, stage(1, cur, cur, S1), "forward stage");
+        HIPCHK(c, stage(2, cur, S1, S2), "forward stage");
+        HIPCHK(c, stage(3, cur, S2, nxt), "forward stage");
+        HIPCHK(c, adj_loss_launch(ag, nxt, n, dpc, dpw, np, dt, loss, s), "loss");
+        cur = nxt;
+    }
+    // ---- reverse sweep
+    AdjArgs A{};
+    A.g = ag;
+    A.n = n;
+    A.dt = dt;
+    A.Vx = at(sVx); A.Fpx = at(sFpx); A.Fmx = at(sFmx); A.gx = at(sGx);
+    A.Vy = at(sVy); A.Fpy = at(sFpy); A.Fmy = at(sFmy); A.gy = at(sGy);
+    A.srcx = (long long*)at(sSx); A.srcy = (long long*)at(sSy);
+    A.cx = at(sCx); A.cy = at(sCy);
+    A.amax = (unsigned long long*)(misc + 4);
+    A.argm = (int*)(misc + 6);
+    A.part = at(sPart);
+    A.nbc = nbc;
+    A.nbd = nbd;
+    A.theta = theta;
+    HIPCHK(c, adj_reset_launch(A, s), "adjoint reset");
+    HIPCHK(c, adj_seed_launch(ag, cur, n, dpc, dpw, np, dt, lam, theta, s), "seed");
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int n0 = sg * K, n1 = std::min(N, n0 + K), m1 = n1 - n0;
+        // recompute the segment, storing the three stage inputs of every step
+        HIPCHK(c, hipMemcpyAsync(S0, ck + (size_t)sg * n5, sizeof(double) * n5, hipMemcpyDeviceToDevice, s), "copy");
+        HIPCHK(c, entry(S0), "recompute entry");
+        for (int m = 0; m < m1 - 1; ++m) {
+            double* u0 = S0 + (size_t)m * n5;
+            HIPCHK(c, stage(1, u0, u0, S1 + (size_t)m * n5), "recompute stage");
+            HIPCHK(c, stage(2, u0, S1 + (size_t)m * n5, S2 + (size_t)m * n5), "recompute stage");
+            HIPCHK(c, stage(3, u0, S2 + (size_t)m * n5, S0 + (size_t)(m + 1) * n5), "recompute stage");
+        }
+        {   // the last step of the segment needs only its first two stage outputs
+            const int m = m1 - 1;
+            double* u0 = S0 + (size_t)m * n5;
+            HIPCHK(c, stage(1, u0, u0, S1 + (size_t)m * n5), "recompute stage");
+            HIPCHK(c, stage(2, u0, S1 + (size_t)m * n5, S2 + (size_t)m * n5), "recompute stage");
+        }
+        for (int m = m1 - 1; m >= 0; --m) {
+            AdjArgs a3 = A;   // stage 3: W = U/3 + 2/3 (V + dt L(V)), V = U^(2)
+            a3.V = S2 + (size_t)m * n5; a3.lamW = lam; a3.lamOut = lA; a3.acc = acc;
+            a3.b = 2.0 / 3.0; a3.a = 1.0 / 3.0; a3.init_acc = 1; a3.add_out = 0;
+            HIPCHK(c, adj_stage(a3, s), "adjoint stage 3");
+            AdjArgs a2 = A;   // stage 2: W = 3/4 U + 1/4 (V + dt L(V)), V = U^(1)
+            a2.V = S1 + (size_t)m * n5; a2.lamW = lA; a2.lamOut = lB; a2.acc = acc;
+            a2.b = 0.25; a2.a = 0.75; a2.init_acc = 0; a2.add_out = 0;
+            HIPCHK(c, adj_stage(a2, s), "adjoint stage 2");
+            AdjArgs a1 = A;   // stage 1: W = V + dt L(V), V = U^n
+            a1.V = S0 + (size_t)m * n5; a1.lamW = lB; a1.lamOut = lA; a1.acc = acc;
+            a1.b = 1.0; a1.a = 0.0; a1.init_acc = 0; a1.add_out = 1;
+            HIPCHK(c, adj_stage(a1, s), "adjoint stage 1");
+            std::swap(lam, acc);
+            if (n0 + m >= 1)
+                HIPCHK(c, adj_seed_launch(ag, S0 + (size_t)m * n5, n, dpc, dpw, np, dt, lam, theta, s), "seed");
+        }
+    }
+    // chain dL/dU0 to the primitives; E0 = p/(gamma-1) + rho |u|^2/2 + rho Y Q adds to dL/dQ
+    HIPCHK(c, adj_chain_launch(ag, W0, lam, n, gW, A.part, theta, s), "chain");
+    return JANC_OK;
+}
+
 }  // namespace
 
 // =============================================================== C ABI
@@ -644,6 +840,15 @@ janc_status janc_plan_create(janc_ctx* c, int nd, const janc_domain* doms, int n
 }
 
 void janc_plan_destroy(janc_plan* p) { plan_free(p); }
+
+janc_status janc_plan_stats(const janc_plan* p, long long* out) {
+    if (!p || !out) return JANC_EINVAL;
+    out[0] = p->cells;
+    out[1] = p->ring_cells;
+    out[2] = p->nblk;
+    out[3] = (long long)p->htiles.size();
+    return JANC_OK;
+}
 
 janc_status janc_plan_set_tile(janc_plan* p, int w) {
     if (!p) return JANC_EINVAL;
@@ -744,9 +949,11 @@ janc_status janc_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph
                          const janc_time* tm, const double* W0, int nsteps, int ckpt_every,
                          int nprobes, const int* probe_cell, const double* probe_w, double* loss,
                          double* dL_dW0, double* dL_dtheta, void* stream) {
-    (void)g; (void)ph; (void)tm; (void)W0; (void)nsteps; (void)ckpt_every; (void)nprobes;
-    (void)probe_cell; (void)probe_w; (void)loss; (void)dL_dW0; (void)dL_dtheta; (void)stream;
-    return fail(c, JANC_EINVAL, "adjoint kernels are not part of this build yet");
+    if (!c || !g || !ph || !tm || !W0 || !loss || !dL_dW0 || !dL_dtheta || nsteps < 1 ||
+        ckpt_every < 1 || nprobes < 0 || (nprobes > 0 && (!probe_cell || !probe_w)))
+        return fail(c, JANC_EINVAL, "bad arguments");
+    return run_adjoint(c, g, ph, tm, W0, nsteps, ckpt_every, nprobes, probe_cell, probe_w, loss,
+                       dL_dW0, dL_dtheta, (hipStream_t)stream);
 }
 
 }  // extern "C"

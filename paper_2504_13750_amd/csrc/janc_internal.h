@@ -124,4 +124,46 @@ hipError_t launch_prim_to_cons(int model, int ns, const DevMech* mech, double ga
                                long long stride_in, long long stride_out, hipStream_t s);
 bool model_supported(int model, int ns);
 
+
+// Discrete adjoint (uniform grid, one-step model): grid constants and the
+// arguments of one stage's reverse sweep.
+struct AdjGrid {
+    int nx, ny, twod, pad;
+    int bc[4];
+    int dir[4];
+    double idx, idy;
+    double gamma, R, Q, Ea, k;
+    const double* dirU;
+};
+
+struct AdjArgs {
+    AdjGrid g;
+    long long n;              // cells
+    const double* V;          // stage input [5][n]
+    const double* lamW;       // adjoint of the stage output [5][n]
+    double* lamOut;           // adjoint of the stage input [5][n]
+    double* acc;              // adjoint of the step start U^n [5][n]
+    double b, a, dt;
+    int init_acc, add_out;
+    double *Vx, *Fpx, *Fmx, *Vy, *Fpy, *Fmy;
+    long long *srcx, *srcy;
+    double *cx, *cy, *gx, *gy;
+    unsigned long long* amax; // [2]
+    int* argm;                // [2]
+    double* part;             // [nblocks][4]
+    int nbc, nbd;             // partial blocks used by C and D
+    double* theta;            // [2]: dL/dQ, dL/dEa
+};
+
+hipError_t adj_stage(const AdjArgs& A, hipStream_t s);
+hipError_t adj_reset_launch(const AdjArgs& A, hipStream_t s);
+hipError_t adj_loss_launch(const AdjGrid& g, const double* U, long long n, const int* pc,
+                           const double* pw, int np, double dt, double* loss, hipStream_t s);
+hipError_t adj_seed_launch(const AdjGrid& g, const double* U, long long n, const int* pc,
+                           const double* pw, int np, double dt, double* lam, double* theta,
+                           hipStream_t s);
+hipError_t adj_chain_launch(const AdjGrid& g, const double* W, const double* lam, long long n,
+                            double* gW, double* part, double* theta, hipStream_t s);
+int adj_partial_blocks(const AdjGrid& g, long long n, int* nbc, int* nbd);
+
 }  // namespace janc

@@ -18,291 +18,9 @@
 //            wavefront and published with one 64-bit atomic max per workgroup.
 // Nothing here is a dense contraction, so there is no MFMA: the work is FP64
 // VALU arithmetic on values staged through LDS.
-#include "janc_internal.h"
+#include "janc_device.h"
 
 namespace janc {
-
-constexpr int WG = 256;
-constexpr double WENO_EPS = 1e-6;
-
-// ------------------------------------------------------------------ small helpers
-__device__ __forceinline__ double sq(double x) { return x * x; }
-
-__device__ __forceinline__ double slot_get(const Reduce& r, int buf, int idx) {
-    return __longlong_as_double((long long)r.buf[(size_t)buf * r.stride + idx]);
-}
-
-__device__ __forceinline__ void slot_max(const Reduce& r, int buf, int idx, double v) {
-    // v >= 0: the bit pattern orders like the value
-    atomicMax(&r.buf[(size_t)buf * r.stride + idx], (unsigned long long)__double_as_longlong(v));
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Workgroup max of three values; thread 0 publishes them.
-__device__ __forceinline__ void publish_max3(const Reduce& r, int buf, int i0, int i1, int i2,
-                                             double v0, double v1, double v2, double* scratch) {
-    v0 = wave_max(v0);
-    v1 = wave_max(v1);
-    v2 = wave_max(v2);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) {
-        scratch[3 * w + 0] = v0;
-        scratch[3 * w + 1] = v1;
-        scratch[3 * w + 2] = v2;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m0 = scratch[0], m1 = scratch[1], m2 = scratch[2];
-        for (int q = 1; q < WG / 64; ++q) {
-            m0 = fmax(m0, scratch[3 * q]);
-            m1 = fmax(m1, scratch[3 * q + 1]);
-            m2 = fmax(m2, scratch[3 * q + 2]);
-        }
-        if (m0 > 0.0) slot_max(r, buf, i0, m0);
-        if (m1 > 0.0) slot_max(r, buf, i1, m1);
-        if (m2 > 0.0) slot_max(r, buf, i2, m2);
-    }
-}
-
-// Coarse-fine ring test for block-local cell (li, lj) (segment masks per side).
-__device__ __forceinline__ bool ring_at(const DevBlock& B, int li, int lj) {
-    const unsigned sx = (unsigned)(lj >> 3) & 31u, sy = (unsigned)(li >> 3) & 31u;
-    return (li < 3 && ((B.ring[0] >> sx) & 1u)) || (li >= B.nx - 3 && ((B.ring[1] >> sx) & 1u)) ||
-           (lj < 3 && ((B.ring[2] >> sy) & 1u)) || (lj >= B.ny - 3 && ((B.ring[3] >> sy) & 1u));
-}
-
-// Effective source of level-`lev` cell (I, J) of domain D: boundary rule first,
-// then the covering block of that level, or the coarser level where the cell is
-// uncovered or a ring cell. Returns a pool cell (>= 0) or -(1 + Dirichlet row);
-// fl gets bit 0 / bit 1 when x / y momentum must be mirrored.
-__device__ long long resolve(const StageArgs& a, const DevDomain& D, int lev, int I, int J,
-                             unsigned& fl) {
-    const int W = D.nx0 << lev, H = D.twod ? (D.ny0 << lev) : 1;
-    if (I < 0 || I >= W) {
-        const int side = (I < 0) ? 0 : 1;
-        switch (D.bc[side]) {
-            case BC_PERIODIC: I = (I < 0) ? I + W : I - W; break;
-            case BC_ZEROGRAD: I = (I < 0) ? 0 : W - 1; break;
-            case BC_SLIPWALL: I = (I < 0) ? -I - 1 : 2 * W - 1 - I; fl ^= 1u; break;
-            default: return -(1ll + D.dir[side]);
-        }
-    }
-    if (J < 0 || J >= H) {
-        const int side = (J < 0) ? 2 : 3;
-        switch (D.bc[side]) {
-            case BC_PERIODIC: J = (J < 0) ? J + H : J - H; break;
-            case BC_ZEROGRAD: J = (J < 0) ? 0 : H - 1; break;
-            case BC_SLIPWALL: J = (J < 0) ? -J - 1 : 2 * H - 1 - J; fl ^= 2u; break;
-            default: return -(1ll + D.dir[side]);
-        }
-    }
-    for (;;) {
-        const int b = a.maps[D.map_off[lev] + (J >> 3) * D.map_w[lev] + (I >> 3)];
-        if (b >= 0) {
-            const DevBlock& B = a.blk[b];
-            const int li = I - B.i0, lj = J - B.j0;
-            if (!ring_at(B, li, lj)) return B.offset + (long long)lj * B.nx + li;
-        }
-        // level 0 tiles the domain and has no ring cells, so this ends
-        --lev;
-        I >>= 1;
-        J >>= 1;
-    }
-}
-
-template <int NU>
-__device__ __forceinline__ void fetch(const StageArgs& a, long long src, unsigned fl,
-                                      const double* Uarr, const double* Tarr, double (&u)[NU],
-                                      double& T) {
-    if (src >= 0) {
-#pragma unroll
-        for (int f = 0; f < NU; ++f) u[f] = Uarr[(size_t)f * a.pool + src];
-        T = Tarr[src];
-    } else {
-        const double* r = a.dirU + (size_t)(-src - 1) * (MAXF + 1);
-#pragma unroll
-        for (int f = 0; f < NU; ++f) u[f] = r[f];
-        T = r[MAXF];
-    }
-    if (fl & 1u) u[1] = -u[1];
-    if (fl & 2u) u[2] = -u[2];
-}
-
-// Velocities and pressure of a stencil cell (Eq. 4.2; T from storage for NASA-7).
-template <int M, int NU>
-__device__ __forceinline__ void halo_prims(const double (&u)[NU], double T, const DevDomain& D,
-                                           const DevMech* mech, double& vx, double& vy,
-                                           double& p) {
-    const double ir = 1.0 / u[0];
-    vx = u[1] * ir;
-    vy = u[2] * ir;
-    if constexpr (M == DETAILED) {
-        double s = 0.0, r = 0.0;
-#pragma unroll
-        for (int k = 0; k < NU - 4; ++k) {
-            s += u[4 + k];
-            r += u[4 + k] * mech->invM[k];
-        }
-        r += (u[0] - s) * mech->invM[NU - 4];
-        p = RU * r * T;
-    } else {
-        double e = u[3] * ir - 0.5 * (vx * vx + vy * vy);
-        if constexpr (M == ONESTEP) e -= u[4] * ir * D.Q;
-        p = (D.gamma - 1.0) * u[0] * e;
-    }
-}
-
-// Newton for T from the internal energy on mixture NASA coefficients
-// (Y fixed during the solve, so the species sums are formed once).
-template <int NS>
-__device__ __forceinline__ unsigned newton_T(const double (&Y)[NS], double e, const DevMech* m,
-                                             double& T, double& cv, double& Rmix) {
-    double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0, b4 = 0.0, b5 = 0.0;
-    Rmix = 0.0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        const double w = Y[k] * m->Rk[k];
-        Rmix += w;
-        b0 += w * m->nasa[k][0];
-        b1 += w * m->nasa[k][1];
-        b2 += w * m->nasa[k][2];
-        b3 += w * m->nasa[k][3];
-        b4 += w * m->nasa[k][4];
-        b5 += w * m->nasa[k][5];
-    }
-    const double c0 = b0 - Rmix, c1 = 0.5 * b1, c2 = b2 * (1.0 / 3.0), c3 = 0.25 * b3,
-                 c4 = 0.2 * b4;
-    unsigned st = STB_NEWTON;
-    for (int it = 0; it < 50; ++it) {
-        const double ec = T * (c0 + T * (c1 + T * (c2 + T * (c3 + T * c4)))) + b5;
-        const double cvv = c0 + T * (b1 + T * (b2 + T * (b3 + T * b4)));
-        const double dT = (ec - e) / cvv;
-        T -= dT;
-        if (!(fabs(dT) <= 1e-12 * fabs(T))) {
-            if (!isfinite(T)) { st = STB_NONFINITE; break; }
-            continue;
-        }
-        st = 0u;
-        break;
-    }
-    cv = c0 + T * (b1 + T * (b2 + T * (b3 + T * b4)));
-    return st;
-}
-
-// State of an owned cell after an update: T (closed form or Newton from Tprev),
-// sound speed and velocities; returns status bits.
-template <int M, int NU>
-__device__ __forceinline__ unsigned owner_state(const double (&u)[NU], double Tprev,
-                                                const DevDomain& D, const DevMech* mech,
-                                                double& T, double& c, double& vx, double& vy) {
-    const double rho = u[0];
-    if (!isfinite(rho)) return STB_NONFINITE;
-    if (!(rho > 0.0)) return STB_NEGATIVE;
-    const double ir = 1.0 / rho;
-    vx = u[1] * ir;
-    vy = u[2] * ir;
-    const double e = u[3] * ir - 0.5 * (vx * vx + vy * vy);
-    double p, gam;
-    unsigned st = 0u;
-    if constexpr (M == DETAILED) {
-        constexpr int NS = NU - 3;
-        double Y[NS];
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < NS - 1; ++k) {
-            Y[k] = u[4 + k] * ir;
-            s += Y[k];
-        }
-        Y[NS - 1] = 1.0 - s;
-        T = Tprev;
-        double cv, Rmix;
-        st = newton_T<NS>(Y, e, mech, T, cv, Rmix);
-        p = rho * Rmix * T;
-        gam = (cv + Rmix) / cv;
-    } else {
-        double ee = e;
-        if constexpr (M == ONESTEP) ee -= u[4] * ir * D.Q;
-        p = (D.gamma - 1.0) * rho * ee;
-        T = p / (rho * D.R);
-        gam = D.gamma;
-    }
-    if (!isfinite(p) || !isfinite(T)) return st | STB_NONFINITE;
-    if (!(p > 0.0) || !(T > 0.0)) return st | STB_NEGATIVE;
-    c = sqrt(gam * p * ir);
-    return st;
-}
-
-// WENO5-JS at i+1/2 from f_{i-2..i+2}: the weighted average of the three
-// candidate stencils in common-denominator form (one division).
-__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
-    const double q0 = 2.0 * a - 7.0 * b + 11.0 * c;
-    const double q1 = -b + 5.0 * c + 2.0 * d;
-    const double q2 = 2.0 * c + 5.0 * d - e;
-    const double t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
-    const double t1 = b - 2.0 * c + d, u1 = b - d;
-    const double t2 = c - 2.0 * d + e, u2 = 3.0 * c - 4.0 * d + e;
-    const double s0 = sq(WENO_EPS + ((13.0 / 12.0) * t0 * t0 + 0.25 * u0 * u0));
-    const double s1 = sq(WENO_EPS + ((13.0 / 12.0) * t1 * t1 + 0.25 * u1 * u1));
-    const double s2 = sq(WENO_EPS + ((13.0 / 12.0) * t2 * t2 + 0.25 * u2 * u2));
-    const double w0 = 0.1 * (s1 * s2), w1 = 0.6 * (s0 * s2), w2 = 0.3 * (s0 * s1);
-    return (w0 * q0 + w1 * q1 + w2 * q2) / (6.0 * (w0 + w1 + w2));
-}
-
-__device__ __forceinline__ double rk_combine(int stage, double u0, double us, double L, double dt) {
-    if (stage == 1) return u0 + dt * L;
-    if (stage == 2) return 0.75 * u0 + 0.25 * (us + dt * L);
-    return (1.0 / 3.0) * u0 + (2.0 / 3.0) * (us + dt * L);
-}
-
-__device__ __forceinline__ double step_dt(const StageArgs& a, int d, int bin) {
-    double dt;
-    if (a.tm.dt_fixed > 0.0) {
-        dt = a.tm.dt_fixed;
-    } else {
-        dt = a.tm.cfl / slot_get(a.red, bin, 2 * a.red.nunits + d);
-    }
-    if (a.tm.t_end > 0.0) {
-        const double rem = a.tm.t_end - a.t[d];
-        if (!(rem > 0.0)) dt = 0.0;
-        else if (dt > rem) dt = rem;
-    }
-    return dt;
-}
-
-// Is level-`lev` cell (I, J) of D under a valid block of level lev+1?
-__device__ __forceinline__ bool covered_by_finer(const StageArgs& a, const DevDomain& D, int lev,
-                                                 int I, int J) {
-    if (lev + 1 >= D.nlevels) return false;
-    const int I2 = 2 * I, J2 = 2 * J;
-    return a.maps[D.map_off[lev + 1] + (J2 >> 3) * D.map_w[lev + 1] + (I2 >> 3)] >= 0;
-}
-
-// Per-launch bookkeeping done by workgroup 0: rotate reduction buffers, dt and t.
-__device__ void stage_bookkeeping(const StageArgs& a, int owner_launch) {
-    const int s = a.stage;
-    const int bclear = (s + 1) % 3;
-    for (int q = threadIdx.x; q < a.red.stride; q += WG) a.red.buf[(size_t)bclear * a.red.stride + q] = 0ull;
-    if (!owner_launch) return;
-    if (s == 1) {
-        const int step = *a.step;
-        for (int d = threadIdx.x; d < a.ndom; d += WG) {
-            const double dt = step_dt(a, d, 0);
-            a.dt[d] = dt;
-            if (a.dt_log && step < a.dt_log_cap) a.dt_log[(size_t)step * a.ndom + d] = dt;
-        }
-    }
-}
-
-__device__ void step_finish(const StageArgs& a) {
-    for (int d = threadIdx.x; d < a.ndom; d += WG) a.t[d] = a.t[d] + a.dt[d];
-    if (threadIdx.x == 0) *a.step = *a.step + 1;
-}
 
 // ------------------------------------------------------------------ the stage tile
 template <int TX, int TY>

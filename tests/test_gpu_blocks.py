@@ -113,6 +113,21 @@ def test_amr_detailed_vs_oracle():
     _cmp_blocks(c, 3)
 
 
+@pytest.mark.parametrize("which", ["small", "config3"])
+def test_plan_ring_cells_match_oracle(which):
+    """Ring-cell counts of the library's segment masks equal the oracle's per-cell rule."""
+    bc = _small_amr() if which == "small" else amr_case()
+    ctx = janc.Context(bc.model, bc.mech)
+    plan = ctx.plan(janc.domains_of(bc), bc.blocks, bc.pool_cells)
+    st = plan.stats()
+    flags = oracle.ring_flags(bc)
+    assert st["cells"] == bc.valid_cells()
+    assert st["ring_cells"] == int(np.sum(flags == 1))
+    assert st["blocks"] == len(bc.blocks)
+    plan.close()
+    ctx.close()
+
+
 def test_bad_table_rejected():
     c = detonation_tube_case(nx=64, ny=16, seed=3)
     bc, _ = _split_uniform(c, [0, 32, 64], [0, 16])
