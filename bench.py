@@ -64,6 +64,28 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2504_13750_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per stage-kernel launch from the committed FETCH_SIZE / WRITE_SIZE
+    counter passes (profiles/), or None when the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.txt")
+    try:
+        with open(path) as fh:
+            hsh, val = fh.read().split()
+    except (OSError, ValueError):
+        return None
+    return float(val) if hsh == kernel_source_hash() else None
+
+
 def cpu_baseline(case, steps, target_s=10.0, max_steps=20):
     """The oracle on the same workload: `steps` steps, extended to about target_s of work."""
     import oracle
@@ -278,7 +300,8 @@ def main():
             "peak": PEAK_FP64_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tf / PEAK_FP64_VALU_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
             "flops_per_cell_stage": stage_flops(2, nU, True),
             "solved_cells_per_launch": solved,
             "avg_launch_ms": stage_avg,
