@@ -10,6 +10,14 @@ namespace janc {
 constexpr int WG = 256;
 constexpr double WENO_EPS = 1e-6;
 
+// Read-only tables (domains, mechanism) viewed through the constant address
+// space: the compiler may then serve workgroup-uniform reads from scalar loads,
+// also after the kernel's own global stores.
+typedef __attribute__((address_space(4))) const DevMech CMech;
+typedef __attribute__((address_space(4))) const DevDomain CDom;
+__device__ __forceinline__ CMech* cmech(const DevMech* p) { return (CMech*)p; }
+__device__ __forceinline__ CDom& cdom(const DevDomain* p, int d) { return ((CDom*)p)[d]; }
+
 // ------------------------------------------------------------------ small helpers
 __device__ __forceinline__ double sq(double x) { return x * x; }
 
@@ -66,7 +74,7 @@ __device__ __forceinline__ bool ring_at(const DevBlock& B, int li, int lj) {
 // then the covering block of that level, or the coarser level where the cell is
 // uncovered or a ring cell. Returns a pool cell (>= 0) or -(1 + Dirichlet row);
 // fl gets bit 0 / bit 1 when x / y momentum must be mirrored.
-__device__ long long resolve(const StageArgs& a, const DevDomain& D, int lev, int I, int J,
+__device__ long long resolve(const StageArgs& a, CDom& D, int lev, int I, int J,
                              unsigned& fl) {
     const int W = D.nx0 << lev, H = D.twod ? (D.ny0 << lev) : 1;
     if (I < 0 || I >= W) {
@@ -120,9 +128,9 @@ __device__ __forceinline__ void fetch(const StageArgs& a, long long src, unsigne
 }
 
 // Velocities and pressure of a stencil cell (Eq. 4.2; T from storage for NASA-7).
-template <int M, int NU>
-__device__ __forceinline__ void halo_prims(const double (&u)[NU], double T, const DevDomain& D,
-                                           const DevMech* mech, double& vx, double& vy,
+template <int M, int NU, class Dom, class Mech>
+__device__ __forceinline__ void halo_prims(const double (&u)[NU], double T, const Dom& D,
+                                           Mech mech, double& vx, double& vy,
                                            double& p) {
     const double ir = 1.0 / u[0];
     vx = u[1] * ir;
@@ -146,7 +154,7 @@ __device__ __forceinline__ void halo_prims(const double (&u)[NU], double T, cons
 // Newton for T from the internal energy on mixture NASA coefficients
 // (Y fixed during the solve, so the species sums are formed once).
 template <int NS>
-__device__ __forceinline__ unsigned newton_T(const double (&Y)[NS], double e, const DevMech* m,
+__device__ __forceinline__ unsigned newton_T(const double (&Y)[NS], double e, CMech* m,
                                              double& T, double& cv, double& Rmix) {
     double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0, b4 = 0.0, b5 = 0.0;
     Rmix = 0.0;
@@ -182,9 +190,9 @@ __device__ __forceinline__ unsigned newton_T(const double (&Y)[NS], double e, co
 
 // State of an owned cell after an update: T (closed form or Newton from Tprev),
 // sound speed and velocities; returns status bits.
-template <int M, int NU>
+template <int M, int NU, class Dom, class Mech>
 __device__ __forceinline__ unsigned owner_state(const double (&u)[NU], double Tprev,
-                                                const DevDomain& D, const DevMech* mech,
+                                                const Dom& D, Mech mech,
                                                 double& T, double& c, double& vx, double& vy) {
     const double rho = u[0];
     if (!isfinite(rho)) return STB_NONFINITE;
@@ -261,11 +269,20 @@ __device__ __forceinline__ double step_dt(const StageArgs& a, int d, int bin) {
 }
 
 // Is level-`lev` cell (I, J) of D under a valid block of level lev+1?
-__device__ __forceinline__ bool covered_by_finer(const StageArgs& a, const DevDomain& D, int lev,
+__device__ __forceinline__ bool covered_by_finer(const StageArgs& a, CDom& D, int lev,
                                                  int I, int J) {
     if (lev + 1 >= D.nlevels) return false;
     const int I2 = 2 * I, J2 = 2 * J;
     return a.maps[D.map_off[lev + 1] + (J2 >> 3) * D.map_w[lev + 1] + (I2 >> 3)] >= 0;
+}
+
+// The dispatcher deals the workgroups of a launch round-robin over the 8 XCDs,
+// each with its own L2. Workgroup b of n is given tile chunk(b) so that each XCD
+// walks one contiguous run of tiles: neighbouring tiles, whose halos overlap,
+// then read them through the same L2. The map is a bijection of [0, n).
+__device__ __forceinline__ int xcd_chunk(int b, int n) {
+    const int q = n >> 3, r = n & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
 }
 
 // Per-launch bookkeeping done by workgroup 0: rotate reduction buffers, dt and t.

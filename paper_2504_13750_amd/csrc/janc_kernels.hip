@@ -53,7 +53,7 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
 
     const int tid = threadIdx.x;
     const DevBlock B = a.blk[tile.block];
-    const DevDomain& D = a.dom[B.domain];
+    CDom& D = cdom(a.dom, B.domain);
     const int lev = B.level;
     const int stage = a.stage;
     const int bin = stage - 1, bout = stage % 3;
@@ -92,7 +92,7 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
                     src = resolve(a, D, lev, B.i0 + bi, B.j0 + bj, fl);
                 double T;
                 fetch<NU>(a, src, fl, a.Uin, a.Tin, ur[q], T);
-                halo_prims<M, NU>(ur[q], T, D, a.mech, vxr[q], vyr[q], pr[q]);
+                halo_prims<M, NU>(ur[q], T, D, cmech(a.mech), vxr[q], vyr[q], pr[q]);
                 if (li >= 0 && li < TX && lj >= 0 && lj < TY) {
                     tcell[lj * TX + li] = T;
                     if constexpr (M == ONESTEP) {
@@ -177,7 +177,7 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
     double sx = 0.0, sy = 0.0, sc = 0.0;
     if (own) {
         double T, c, vx, vy;
-        const unsigned st = owner_state<M, NU>(unew, tcell[olj * TX + oli], D, a.mech, T, c, vx, vy);
+        const unsigned st = owner_state<M, NU>(unew, tcell[olj * TX + oli], D, cmech(a.mech), T, c, vx, vy);
         a.Tout[oc] = T;
         if (st) atomicOr(a.status, st);
         const bool skip = (stage == 3) && B.fine_child &&
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(WG) void stage_kernel(StageArgs a, int first_tile, 
     constexpr int L2 = Geom<TX, TY>::LDS, L1 = Geom<WG, 1>::LDS;
     __shared__ double smem[(L2 > L1) ? L2 : L1];
     if (blockIdx.x == 0) stage_bookkeeping(a, owner_launch);
-    const Tile tile = a.tiles[first_tile + blockIdx.x];
+    const Tile tile = a.tiles[first_tile + xcd_chunk(blockIdx.x, gridDim.x)];
     if (HAS1D && tile.kind == 1) {
         if constexpr (HAS1D) stage_tile<M, NU, WG, 1>(a, tile, smem);
     } else {
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(WG) void init_kernel(StageArgs a) {
     __shared__ double scratch[16];
     const Tile tile = a.tiles[blockIdx.x];
     const DevBlock B = a.blk[tile.block];
-    const DevDomain& D = a.dom[B.domain];
+    CDom& D = cdom(a.dom, B.domain);
     const CellRef r = tile_cell(a, tile, B);
     const int lev = B.level, slot = D.slot0 + lev;
     const double idx = (double)(1 << lev) / D.dx0, idy = (double)(1 << lev) / D.dy0;
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(WG) void init_kernel(StageArgs a) {
 #pragma unroll
         for (int f = 0; f < NU; ++f) u[f] = a.Uin[(size_t)f * a.pool + r.c];
         double T, c, vx, vy;
-        const unsigned st = owner_state<M, NU>(u, a.Tin[r.c], D, a.mech, T, c, vx, vy);
+        const unsigned st = owner_state<M, NU>(u, a.Tin[r.c], D, cmech(a.mech), T, c, vx, vy);
         a.Tout[r.c] = T;
         if (st) atomicOr(a.status, st);
         else {
@@ -273,12 +273,14 @@ __global__ __launch_bounds__(WG) void init_kernel(StageArgs a) {
 
 // Point-implicit chemistry (Eq. 4.12-4.13) on rho Y_1 .. rho Y_{Ns-1} of each
 // solved cell, then Newton for the new T and the maxima for the next step.
-// X and dq/dX live in LDS (indexed by a wave-uniform species number); the
-// (Ns-1)^2 Jacobian and its LU factorization live in registers.
+// Mechanism tables are read as wave-uniform scalar loads. Per-thread columns in
+// LDS hold X, the species Gibbs terms and the derivative row dq/dX of the
+// current reaction (indexed by wave-uniform species numbers); the (Ns-1)^2
+// Jacobian, the production rates and the LU factorization live in registers.
 template <int NS>
-__device__ __forceinline__ void chem_cell(const DevMech* m, double* Xs, double* dqs, double rho,
-                                          double T, double (&rY)[NS - 1], double dt,
-                                          unsigned& st) {
+__device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, double* dqs,
+                                          double rho, double T, const double (&rY)[NS - 1],
+                                          double dt, double (&w)[NS - 1], unsigned& st) {
     constexpr int NT = NS - 1;
     const int tid = threadIdx.x;
     // LDS column per thread: X[0..NS-1], X[NS] = 1 (padding of the molecule lists)
@@ -292,14 +294,13 @@ __device__ __forceinline__ void chem_cell(const DevMech* m, double* Xs, double* 
     Xs[NS * WG + tid] = 1.0;
     const double lnT = log(T), invT = 1.0 / T;
     const double lnC = log(PATM / RU) - lnT;      // ln(p_atm / (R_u T))
-    double gt[NS];                                 // h/(R T) - s/R per species
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-        const double* c = m->nasa[j];
-        gt[j] = c[0] * (1.0 - lnT) - T * (0.5 * c[1] + T * (c[2] * (1.0 / 6.0) +
-                T * (c[3] * (1.0 / 12.0) + T * (c[4] * 0.05)))) + c[5] * invT - c[6];
+    for (int j = 0; j < NS; ++j) {                 // h/(R T) - s/R per species
+        gts[j * WG + tid] = m->nasa[j][0] * (1.0 - lnT) -
+                T * (0.5 * m->nasa[j][1] + T * (m->nasa[j][2] * (1.0 / 6.0) +
+                T * (m->nasa[j][3] * (1.0 / 12.0) + T * (m->nasa[j][4] * 0.05)))) +
+                m->nasa[j][5] * invT - m->nasa[j][6];
     }
-    double w[NT];
     double J[NT][NT];
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
@@ -307,14 +308,15 @@ __device__ __forceinline__ void chem_cell(const DevMech* m, double* Xs, double* 
 #pragma unroll
         for (int q = 0; q < NT; ++q) J[k][q] = 0.0;
     }
-    for (int i = 0; i < m->nr; ++i) {
+    const int nr = m->nr;
+    for (int i = 0; i < nr; ++i) {
         const double lnkf = m->lnA[i] + m->b[i] * lnT - m->EaR[i] * invT;
         const double kf = exp(lnkf);
         double kb = 0.0;
         if (m->rev[i]) {
             double sg = 0.0;
 #pragma unroll
-            for (int j = 0; j < NS; ++j) sg += (double)m->dnu[i][j] * gt[j];
+            for (int j = 0; j < NS; ++j) sg += (double)m->dnu[i][j] * gts[j * WG + tid];
             // K_eq = exp(-sum dnu g) (p_atm/(R_u T))^(sum dnu), Eq. 4.9
             kb = exp(lnkf + sg - (double)m->dnsum[i] * lnC);
         }
@@ -323,8 +325,8 @@ __device__ __forceinline__ void chem_cell(const DevMech* m, double* Xs, double* 
         const double xf0 = Xs[f0 * WG + tid], xf1 = Xs[f1 * WG + tid], xf2 = Xs[f2 * WG + tid];
         const double xb0 = Xs[r0 * WG + tid], xb1 = Xs[r1 * WG + tid], xb2 = Xs[r2 * WG + tid];
         const double Rf = kf * (xf0 * xf1 * xf2), Rb = kb * (xb0 * xb1 * xb2);
-        double ctb = 1.0;
         const bool tbr = m->has_tb[i] != 0;
+        double ctb = 1.0;
         if (tbr) {
             ctb = 0.0;
 #pragma unroll
@@ -336,13 +338,14 @@ __device__ __forceinline__ void chem_cell(const DevMech* m, double* Xs, double* 
         for (int k = 0; k < NT; ++k) w[k] += m->Mdnu[i][k] * q;
         // dq/dX_j into LDS (padding slot NS absorbs the entries of missing molecules)
 #pragma unroll
-        for (int j = 0; j <= NS; ++j) dqs[j * WG + tid] = tbr ? m->tb[i][j < NS ? j : 0] * net * (j < NS ? 1.0 : 0.0) : 0.0;
-        dqs[f0 * WG + tid] += ctb * kf * (xf1 * xf2);
-        dqs[f1 * WG + tid] += ctb * kf * (xf0 * xf2);
-        dqs[f2 * WG + tid] += ctb * kf * (xf0 * xf1);
-        dqs[r0 * WG + tid] -= ctb * kb * (xb1 * xb2);
-        dqs[r1 * WG + tid] -= ctb * kb * (xb0 * xb2);
-        dqs[r2 * WG + tid] -= ctb * kb * (xb0 * xb1);
+        for (int j = 0; j <= NS; ++j) dqs[j * WG + tid] = (tbr && j < NS) ? m->tb[i][j] * net : 0.0;
+        const double cf = ctb * kf, cb = ctb * kb;
+        dqs[f0 * WG + tid] += cf * (xf1 * xf2);
+        dqs[f1 * WG + tid] += cf * (xf0 * xf2);
+        dqs[f2 * WG + tid] += cf * (xf0 * xf1);
+        dqs[r0 * WG + tid] -= cb * (xb1 * xb2);
+        dqs[r1 * WG + tid] -= cb * (xb0 * xb2);
+        dqs[r2 * WG + tid] -= cb * (xb0 * xb1);
         // d(rho Y_m): dX_j/d(rho Y_m) = delta_jm / M_m - delta_{j,last} / M_last
         const double dlast = dqs[NT * WG + tid] * m->invM[NT];
         double Dm[NT];
@@ -357,47 +360,50 @@ __device__ __forceinline__ void chem_cell(const DevMech* m, double* Xs, double* 
             }
         }
     }
-    // (I - dt J) dU = dt w, Gaussian elimination without pivoting
-    double A[NT][NT], bvec[NT];
+    // (I - dt J) dU = dt w, Gaussian elimination without pivoting, in place;
+    // w returns the increment of rho Y_1 .. rho Y_{Ns-1}
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
 #pragma unroll
-        for (int q = 0; q < NT; ++q) A[k][q] = (k == q ? 1.0 : 0.0) - dt * J[k][q];
-        bvec[k] = w[k] * dt;
+        for (int q = 0; q < NT; ++q) J[k][q] = (k == q ? 1.0 : 0.0) - dt * J[k][q];
+        w[k] = w[k] * dt;
     }
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
-        const double piv = A[c][c];
+        const double piv = J[c][c];
         if (!(fabs(piv) > 0.0) || !isfinite(piv)) st |= STB_NONFINITE;
         const double ip = 1.0 / piv;
 #pragma unroll
         for (int r = c + 1; r < NT; ++r) {
-            const double fct = A[r][c] * ip;
+            const double fct = J[r][c] * ip;
 #pragma unroll
-            for (int q = c + 1; q < NT; ++q) A[r][q] -= fct * A[c][q];
-            bvec[r] -= fct * bvec[c];
+            for (int q = c + 1; q < NT; ++q) J[r][q] -= fct * J[c][q];
+            w[r] -= fct * w[c];
         }
     }
 #pragma unroll
     for (int r = NT - 1; r >= 0; --r) {
-        double sacc = bvec[r];
+        double sacc = w[r];
 #pragma unroll
-        for (int q = r + 1; q < NT; ++q) sacc -= A[r][q] * bvec[q];
-        bvec[r] = sacc / A[r][r];
+        for (int q = r + 1; q < NT; ++q) sacc -= J[r][q] * w[q];
+        w[r] = sacc / J[r][r];
     }
-#pragma unroll
-    for (int k = 0; k < NT; ++k) rY[k] += bvec[k];
 }
 
+#ifndef CHEM_WAVES
+#define CHEM_WAVES 1
+#endif
 template <int NS>
-__global__ __launch_bounds__(WG) void chem_kernel(StageArgs a) {
+__global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
     constexpr int NU = NS + 3;
     __shared__ double Xs[(NS + 1) * WG];
+    __shared__ double gts[NS * WG];
     __shared__ double dqs[(NS + 1) * WG];
     __shared__ double scratch[16];
     const Tile tile = a.tiles[blockIdx.x];
     const DevBlock B = a.blk[tile.block];
-    const DevDomain& D = a.dom[B.domain];
+    CDom& D = cdom(a.dom, B.domain);
+    CMech* mech = cmech(a.mech);
     const CellRef r = tile_cell(a, tile, B);
     const int lev = B.level, slot = D.slot0 + lev;
     const double dt = a.dt[B.domain];
@@ -405,31 +411,34 @@ __global__ __launch_bounds__(WG) void chem_kernel(StageArgs a) {
     if (blockIdx.x == 0) step_finish(a);
     if (!(dt > 0.0)) return;
     double sx = 0.0, sy = 0.0, sc = 0.0;
-    double u[NU];
-    double T = 1.0;
     unsigned st = 0u;
+    double dY[NS - 1];
+    double T = 1.0;
+    {
+        // inactive lanes run the same arithmetic on a harmless state
+        double rho = 1.0;
+        double rY[NS - 1];
+#pragma unroll
+        for (int k = 0; k < NS - 1; ++k) rY[k] = 0.0;
+        if (r.own) {
+            rho = a.Uout[r.c];
+#pragma unroll
+            for (int k = 0; k < NS - 1; ++k) rY[k] = a.Uout[(size_t)(4 + k) * a.pool + r.c];
+            T = a.Tout[r.c];
+        }
+        chem_cell<NS>(mech, Xs, gts, dqs, rho, T, rY, dt, dY, st);
+    }
     if (r.own) {
+        double u[NU];
 #pragma unroll
         for (int f = 0; f < NU; ++f) u[f] = a.Uout[(size_t)f * a.pool + r.c];
-        T = a.Tout[r.c];
-    } else {
-        // inactive lanes run the same arithmetic on a harmless state
-#pragma unroll
-        for (int f = 0; f < NU; ++f) u[f] = 0.0;
-        u[0] = 1.0;
-    }
-    double rY[NS - 1];
-#pragma unroll
-    for (int k = 0; k < NS - 1; ++k) rY[k] = u[4 + k];
-    chem_cell<NS>(a.mech, Xs, dqs, u[0], T, rY, dt, st);
-    if (r.own) {
 #pragma unroll
         for (int k = 0; k < NS - 1; ++k) {
-            u[4 + k] = rY[k];
-            a.Uout[(size_t)(4 + k) * a.pool + r.c] = rY[k];
+            u[4 + k] += dY[k];
+            a.Uout[(size_t)(4 + k) * a.pool + r.c] = u[4 + k];
         }
         double Tn, c, vx, vy;
-        st |= owner_state<DETAILED, NU>(u, T, D, a.mech, Tn, c, vx, vy);
+        st |= owner_state<DETAILED, NU>(u, T, D, mech, Tn, c, vx, vy);
         a.Tout[r.c] = Tn;
         if (st) atomicOr(a.status, st);
         const bool skip = B.fine_child && covered_by_finer(a, D, lev, r.I, r.J);
@@ -450,7 +459,7 @@ template <int M, int NU>
 __global__ __launch_bounds__(WG) void restrict_kernel(StageArgs a, const int* fine_blocks) {
     __shared__ double scratch[16];
     const DevBlock B = a.blk[fine_blocks[blockIdx.x]];
-    const DevDomain& D = a.dom[B.domain];
+    CDom& D = cdom(a.dom, B.domain);
     const int lev = B.level;
     const double dt = a.dt[B.domain];
     if (!(dt > 0.0)) return;
@@ -481,7 +490,7 @@ __global__ __launch_bounds__(WG) void restrict_kernel(StageArgs a, const int* fi
 #pragma unroll
         for (int f = 0; f < NU; ++f) a.Uout[(size_t)f * a.pool + cpar] = mean[f];
         double T, c, vx, vy;
-        const unsigned st = owner_state<M, NU>(mean, a.Tout[cpar], D, a.mech, T, c, vx, vy);
+        const unsigned st = owner_state<M, NU>(mean, a.Tout[cpar], D, cmech(a.mech), T, c, vx, vy);
         a.Tout[cpar] = T;
         if (st) atomicOr(a.status, st);
         else {
@@ -498,7 +507,7 @@ __global__ __launch_bounds__(WG) void restrict_kernel(StageArgs a, const int* fi
 template <int NU>
 __global__ __launch_bounds__(WG) void ring_fill_kernel(StageArgs a, const int* ring_blocks) {
     const DevBlock B = a.blk[ring_blocks[blockIdx.x]];
-    const DevDomain& D = a.dom[B.domain];
+    CDom& D = cdom(a.dom, B.domain);
     if (!(a.dt[B.domain] > 0.0)) return;
     for (int q = threadIdx.x; q < B.nx * B.ny; q += WG) {
         const int lj = q / B.nx, li = q - lj * B.nx;
