@@ -134,291 +134,323 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return s;
 }
 
-// Wave speeds of an interior cell as the forward reductions compute them.
-__device__ __forceinline__ void cell_speeds(const AdjArgs& A, long long c, double& sx, double& sy) {
-    double V[NU5];
+__device__ __forceinline__ double block_max(double v, double* sh) {
 #pragma unroll
-    for (int f = 0; f < NU5; ++f) V[f] = A.V[(size_t)f * A.n + c];
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = sh[0];
+    for (int q = 1; q < AWG / 64; ++q) r = fmax(r, sh[q]);
+    return r;
+}
+
+__device__ __forceinline__ int block_min(int v, int* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    int r = sh[0];
+    for (int q = 1; q < AWG / 64; ++q) r = min(r, sh[q]);
+    return r;
+}
+
+// Completion count of a launch: true in the one workgroup that finishes last,
+// after which it sees every other workgroup's stores. Each thread releases its
+// own stores at device scope before the count; the counter is reset for reuse.
+__device__ __forceinline__ bool last_block(unsigned* cnt, unsigned nblocks, int* flag) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) *flag = (atomicAdd(cnt, 1u) == nblocks - 1) ? 1 : 0;
+    __syncthreads();
+    if (!*flag) return false;
+    __threadfence();
+    if (threadIdx.x == 0) *cnt = 0u;
+    return true;
+}
+
+// Wave speeds of a cell of state V as the forward reductions compute them.
+__device__ __forceinline__ void cell_speeds_of(const AdjGrid& g, const double* V, long long n,
+                                               long long c, double& sx, double& sy) {
+    double u[NU5];
+#pragma unroll
+    for (int f = 0; f < NU5; ++f) u[f] = V[(size_t)f * n + c];
     DevDomain D{};
-    D.gamma = A.g.gamma;
-    D.R = A.g.R;
-    D.Q = A.g.Q;
+    D.gamma = g.gamma;
+    D.R = g.R;
+    D.Q = g.Q;
     double T, cs, vx, vy;
-    owner_state<ONESTEP, NU5>(V, 0.0, D, nullptr, T, cs, vx, vy);
+    owner_state<ONESTEP, NU5>(u, 0.0, D, nullptr, T, cs, vx, vy);
     sx = fabs(vx) + cs;
     sy = fabs(vy) + cs;
 }
 
-__global__ __launch_bounds__(AWG) void adj_alpha(AdjArgs A) {
+// A: alpha_x, alpha_y of every stage input of a run of steps and the lowest
+// cell attaining each (block maxima, then the last workgroup of the slice).
+__global__ __launch_bounds__(AWG) void adj_alpha(AlphaArgs P) {
+    __shared__ double sh[8];
+    __shared__ int ish[8];
+    __shared__ int flag;
+    const int z = blockIdx.y;
+    const double* V = P.base[z % 3] + (size_t)(z / 3) * P.step_stride;
     const long long c = (long long)blockIdx.x * AWG + threadIdx.x;
-    if (c >= A.n) return;
-    double sx, sy;
-    cell_speeds(A, c, sx, sy);
-    atomicMax(&A.amax[0], (unsigned long long)__double_as_longlong(sx));
-    atomicMax(&A.amax[1], (unsigned long long)__double_as_longlong(sy));
-}
-
-__global__ __launch_bounds__(AWG) void adj_argmax(AdjArgs A) {
-    const long long c = (long long)blockIdx.x * AWG + threadIdx.x;
-    if (c >= A.n) return;
-    double sx, sy;
-    cell_speeds(A, c, sx, sy);
-    if (__double_as_longlong(sx) == (long long)A.amax[0]) atomicMin(&A.argm[0], (int)c);
-    if (__double_as_longlong(sy) == (long long)A.amax[1]) atomicMin(&A.argm[1], (int)c);
-}
-
-// A1: strip cells -> state, ghost source, split fluxes.
-__global__ __launch_bounds__(AWG) void adj_prep(AdjArgs A) {
-    const int q = blockIdx.x * AWG + threadIdx.x;
-    const AdjGrid& g = A.g;
-    const int nxs = xs_n(g), nys = ys_n(g);
-    if (q >= nxs + nys) return;
-    const bool xdir = q < nxs;
-    int i, j, s;
-    if (xdir) {
-        j = q / (g.nx + 6);
-        i = q - j * (g.nx + 6) - 3;
-        s = q;
-    } else {
-        s = q - nxs;
-        const int yj = s / g.nx;
-        i = s - yj * g.nx;
-        j = yj - 3;
+    double sx = -1.0, sy = -1.0;
+    if (c < P.n) cell_speeds_of(P.g, V, P.n, c, sx, sy);
+    const double mx = block_max(sx, sh), my = block_max(sy, sh);
+    const int ix = block_min((c < P.n && sx == mx) ? (int)c : 0x7fffffff, ish);
+    const int iy = block_min((c < P.n && sy == my) ? (int)c : 0x7fffffff, ish);
+    double* part = P.part + (size_t)z * P.nbd * 4;
+    if (threadIdx.x == 0) {
+        part[(size_t)blockIdx.x * 4 + 0] = mx;
+        part[(size_t)blockIdx.x * 4 + 1] = my;
+        part[(size_t)blockIdx.x * 4 + 2] = (double)ix;
+        part[(size_t)blockIdx.x * 4 + 3] = (double)iy;
     }
-    unsigned fl;
-    const long long src = usrc(g, i, j, fl);
-    double V[NU5];
-    load_src(A, src, fl, V);
-    const double al = __longlong_as_double((long long)A.amax[xdir ? 0 : 1]);
-    DevDomain D{};
-    D.gamma = g.gamma;
-    D.Q = g.Q;
-    double vx, vy, p;
-    halo_prims<ONESTEP, NU5>(V, 0.0, D, nullptr, vx, vy, p);
-    const double vn = xdir ? vx : vy;
-    const int ns = xdir ? nxs : nys;
-    double* Vo = xdir ? A.Vx : A.Vy;
-    double* Fp = xdir ? A.Fpx : A.Fpy;
-    double* Fm = xdir ? A.Fmx : A.Fmy;
-    (xdir ? A.srcx : A.srcy)[s] = (src >= 0) ? (src | ((long long)fl << 40)) : src;
-#pragma unroll
-    for (int f = 0; f < NU5; ++f) {
-        double F = V[f] * vn;
-        if (f == (xdir ? 1 : 2)) F += p;
-        if (f == 3) F = (V[f] + p) * vn;
-        Vo[(size_t)f * ns + s] = V[f];
-        Fp[(size_t)f * ns + s] = 0.5 * (F + al * V[f]);
-        Fm[(size_t)f * ns + s] = 0.5 * (F - al * V[f]);
+    if (!last_block(P.cnt + z, gridDim.x, &flag)) return;
+    double bx = -1.0, by = -1.0;
+    for (int q = threadIdx.x; q < P.nbd; q += AWG) {
+        bx = fmax(bx, part[(size_t)q * 4 + 0]);
+        by = fmax(by, part[(size_t)q * 4 + 1]);
+    }
+    const double gx = block_max(bx, sh), gy = block_max(by, sh);
+    int jx = 0x7fffffff, jy = 0x7fffffff;
+    for (int q = threadIdx.x; q < P.nbd; q += AWG) {
+        if (part[(size_t)q * 4 + 0] == gx) jx = min(jx, (int)part[(size_t)q * 4 + 2]);
+        if (part[(size_t)q * 4 + 1] == gy) jy = min(jy, (int)part[(size_t)q * 4 + 3]);
+    }
+    jx = block_min(jx, ish);
+    jy = block_min(jy, ish);
+    if (threadIdx.x == 0) {
+        P.alpha[2 * z] = gx;
+        P.alpha[2 * z + 1] = gy;
+        P.argm[2 * z] = jx;
+        P.argm[2 * z + 1] = jy;
     }
 }
 
-// B: interfaces -> reverse WENO weights.
+// Split flux of component f at a stencil point (the forward's own formula).
+__device__ __forceinline__ void split_flux(const double (&V)[NU5], double vn, double p, int f,
+                                           bool xdir, double al, double& Fp, double& Fm) {
+    double F = V[f] * vn;
+    if (f == (xdir ? 1 : 2)) F += p;
+    if (f == 3) F = (V[f] + p) * vn;
+    Fp = 0.5 * (F + al * V[f]);
+    Fm = 0.5 * (F - al * V[f]);
+}
+
+// B: per interface, mu_Fhat = b dt (mu_right - mu_left)/dx and the reverse of
+// both WENO5 reconstructions; the six stencil states and their split fluxes
+// are formed here from the stage input.
 __global__ __launch_bounds__(AWG) void adj_iface(AdjArgs A) {
     const int q = blockIdx.x * AWG + threadIdx.x;
     const AdjGrid& g = A.g;
     const int nix = (g.nx + 1) * g.ny, niy = g.twod ? g.nx * (g.ny + 1) : 0;
     if (q >= nix + niy) return;
     const double mscale = A.b * A.dt;
-    if (q < nix) {
-        const int j = q / (g.nx + 1), k = q - j * (g.nx + 1);
-        const int nxs = xs_n(g);
-        const int base = j * (g.nx + 6) + k;
-#pragma unroll
-        for (int f = 0; f < NU5; ++f) {
-            const double mr = (k < g.nx) ? A.lamW[(size_t)f * A.n + (size_t)j * g.nx + k] : 0.0;
-            const double ml = (k > 0) ? A.lamW[(size_t)f * A.n + (size_t)j * g.nx + k - 1] : 0.0;
-            const double fb = mscale * (mr - ml) * g.idx;
-            const double* P = A.Fpx + (size_t)f * nxs + base;
-            const double* M = A.Fmx + (size_t)f * nxs + base;
-            double gp[5], gm[5];
-            weno5_adj(P[0], P[1], P[2], P[3], P[4], fb, gp);
-            weno5_adj(M[5], M[4], M[3], M[2], M[1], fb, gm);
-            double* out = A.cx + (size_t)f * 10 * nix;
-#pragma unroll
-            for (int m = 0; m < 5; ++m) {
-                out[(size_t)m * nix + q] = gp[m];
-                out[(size_t)(5 + m) * nix + q] = gm[4 - m];
-            }
-        }
+    const bool xdir = q < nix;
+    int r, i0, j0, k, len, lidx;
+    if (xdir) {
+        r = q;
+        j0 = q / (g.nx + 1);
+        k = q - j0 * (g.nx + 1);
+        i0 = k - 3;
+        len = g.nx;
+        lidx = j0 * g.nx + k;
     } else {
-        const int r = q - nix;
-        const int k = r / g.nx, i = r - k * g.nx;
-        const int nys = ys_n(g);
+        r = q - nix;
+        k = r / g.nx;
+        i0 = r - k * g.nx;
+        j0 = k - 3;
+        len = g.ny;
+        lidx = k * g.nx + i0;
+    }
+    const long long lstep = xdir ? 1 : g.nx;
+    const double al = A.alpha[xdir ? 0 : 1];
+    const double ih = xdir ? g.idx : g.idy;
+    // stencil points t = 0..5 at positions k-3 .. k+2 along the sweep
+    double V[6][NU5], vn[6], pp[6];
+    DevDomain D{};
+    D.gamma = g.gamma;
+    D.Q = g.Q;
 #pragma unroll
-        for (int f = 0; f < NU5; ++f) {
-            const double mr = (k < g.ny) ? A.lamW[(size_t)f * A.n + (size_t)k * g.nx + i] : 0.0;
-            const double ml = (k > 0) ? A.lamW[(size_t)f * A.n + (size_t)(k - 1) * g.nx + i] : 0.0;
-            const double fb = mscale * (mr - ml) * g.idy;
-            const double* P = A.Fpy + (size_t)f * nys + (size_t)k * g.nx + i;
-            const double* M = A.Fmy + (size_t)f * nys + (size_t)k * g.nx + i;
-            const int X = g.nx;
-            double gp[5], gm[5];
-            weno5_adj(P[0], P[X], P[2 * X], P[3 * X], P[4 * X], fb, gp);
-            weno5_adj(M[5 * X], M[4 * X], M[3 * X], M[2 * X], M[X], fb, gm);
-            double* out = A.cy + (size_t)f * 10 * niy;
+    for (int t = 0; t < 6; ++t) {
+        unsigned fl;
+        const long long src = xdir ? usrc(g, i0 + t, j0, fl) : usrc(g, i0, j0 + t, fl);
+        load_src(A, src, fl, V[t]);
+        double vx, vy;
+        halo_prims<ONESTEP, NU5>(V[t], 0.0, D, nullptr, vx, vy, pp[t]);
+        vn[t] = xdir ? vx : vy;
+    }
+    double* outb = xdir ? A.cx : A.cy;
+    const int ni = xdir ? nix : niy;
 #pragma unroll
-            for (int m = 0; m < 5; ++m) {
-                out[(size_t)m * niy + r] = gp[m];
-                out[(size_t)(5 + m) * niy + r] = gm[4 - m];
-            }
+    for (int f = 0; f < NU5; ++f) {
+        const double mr = (k < len) ? A.lamW[(size_t)f * A.n + lidx] : 0.0;
+        const double ml = (k > 0) ? A.lamW[(size_t)f * A.n + lidx - lstep] : 0.0;
+        const double fb = mscale * (mr - ml) * ih;
+        double Fp[6], Fm[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) split_flux(V[t], vn[t], pp[t], f, xdir, al, Fp[t], Fm[t]);
+        double gp[5], gm[5];
+        weno5_adj(Fp[0], Fp[1], Fp[2], Fp[3], Fp[4], fb, gp);
+        weno5_adj(Fm[5], Fm[4], Fm[3], Fm[2], Fm[1], fb, gm);
+        double* out = outb + (size_t)f * 10 * ni;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            out[(size_t)m * ni + r] = gp[m];
+            out[(size_t)(5 + m) * ni + r] = gm[4 - m];
         }
     }
 }
 
-// C: strip cells -> adjoint of the strip state (flux Jacobian + alpha term).
-__global__ __launch_bounds__(AWG) void adj_gather(AdjArgs A) {
-    __shared__ double sh[8];
-    const int q = blockIdx.x * AWG + threadIdx.x;
+// Gather of the split-flux adjoints of strip position xi (x sweep: row j, xi in
+// 0..nx+5) or yj (y sweep: column i, yj in 0..ny+5) from the 5 + 5 interfaces
+// whose stencils read it.
+__device__ __forceinline__ void gather_strip(const AdjArgs& A, bool xdir, int i, int j, int xi,
+                                             double (&mp)[NU5], double (&mm)[NU5]) {
     const AdjGrid& g = A.g;
-    const int nxs = xs_n(g), nys = ys_n(g);
-    const int nix = (g.nx + 1) * g.ny, niy = g.twod ? g.nx * (g.ny + 1) : 0;
-    double pax = 0.0, pay = 0.0, pQ = 0.0;
-    if (q < nxs + nys) {
-        const bool xdir = q < nxs;
-        const int ns = xdir ? nxs : nys;
-        const int s = xdir ? q : q - nxs;
-        double V[NU5], mp[NU5], mm[NU5];
+    const int len = xdir ? g.nx : g.ny;
+    const int ni = xdir ? (g.nx + 1) * g.ny : g.nx * (g.ny + 1);
 #pragma unroll
-        for (int f = 0; f < NU5; ++f) V[f] = (xdir ? A.Vx : A.Vy)[(size_t)f * ns + s];
-        if (xdir) {
-            const int j = s / (g.nx + 6), xi = s - j * (g.nx + 6);
+    for (int f = 0; f < NU5; ++f) {
+        const double* cf = (xdir ? A.cx : A.cy) + (size_t)f * 10 * ni;
+        double ap = 0.0, am = 0.0;
 #pragma unroll
-            for (int f = 0; f < NU5; ++f) {
-                const double* cf = A.cx + (size_t)f * 10 * nix;
-                double ap = 0.0, am = 0.0;
-#pragma unroll
-                for (int m = 0; m < 5; ++m) {
-                    const int Ip = xi - m, Im = xi - 1 - m;
-                    if (Ip >= 0 && Ip <= g.nx) ap += cf[(size_t)m * nix + j * (g.nx + 1) + Ip];
-                    if (Im >= 0 && Im <= g.nx) am += cf[(size_t)(5 + m) * nix + j * (g.nx + 1) + Im];
-                }
-                mp[f] = ap;
-                mm[f] = am;
-            }
-        } else {
-            const int yj = s / g.nx, i = s - yj * g.nx;
-#pragma unroll
-            for (int f = 0; f < NU5; ++f) {
-                const double* cf = A.cy + (size_t)f * 10 * niy;
-                double ap = 0.0, am = 0.0;
-#pragma unroll
-                for (int m = 0; m < 5; ++m) {
-                    const int Ip = yj - m, Im = yj - 1 - m;
-                    if (Ip >= 0 && Ip <= g.ny) ap += cf[(size_t)m * niy + Ip * g.nx + i];
-                    if (Im >= 0 && Im <= g.ny) am += cf[(size_t)(5 + m) * niy + Im * g.nx + i];
-                }
-                mp[f] = ap;
-                mm[f] = am;
-            }
+        for (int m = 0; m < 5; ++m) {
+            const int Ip = xi - m, Im = xi - 1 - m;
+            const int rp = xdir ? j * (g.nx + 1) + Ip : Ip * g.nx + i;
+            const int rm = xdir ? j * (g.nx + 1) + Im : Im * g.nx + i;
+            if (Ip >= 0 && Ip <= len) ap += cf[(size_t)m * ni + rp];
+            if (Im >= 0 && Im <= len) am += cf[(size_t)(5 + m) * ni + rm];
         }
-        const PGrad P = pgrad(g, V);
-        const double al = __longlong_as_double((long long)A.amax[xdir ? 0 : 1]);
-        double a[NU5], bq[NU5], out[NU5];
-#pragma unroll
-        for (int f = 0; f < NU5; ++f) {
-            a[f] = 0.5 * (mp[f] + mm[f]);
-            bq[f] = 0.5 * (mp[f] - mm[f]);
-        }
-        const double rho = V[0], E = V[3], r = V[4];
-        const double ir = 1.0 / rho;
-        // normal velocity w, tangential t; normal momentum index nm, tangential tm
-        const double w = xdir ? P.u : P.v, t = xdir ? P.v : P.u;
-        const double pw = xdir ? P.pm : P.pn, pt = xdir ? P.pn : P.pm;
-        // flux components: mass, normal momentum, tangential momentum, energy, species
-        const double a_mass = a[0], a_nm = a[xdir ? 1 : 2], a_tm = a[xdir ? 2 : 1];
-        const double a_E = a[3], a_r = a[4];
-        double d_rho = a_nm * (-w * w + P.pr) + a_tm * (-w * t) + a_E * (-w * (E + P.p) * ir + w * P.pr) +
-                       a_r * (-r * w * ir);
-        double d_nm = a_mass + a_nm * (2.0 * w + pw) + a_tm * t + a_E * ((E + P.p) * ir + w * pw) + a_r * (r * ir);
-        double d_tm = a_nm * pt + a_tm * w + a_E * w * pt;
-        double d_E = a_nm * P.pE + a_E * w * (1.0 + P.pE);
-        double d_r = a_nm * P.pY + a_E * w * P.pY + a_r * w;
-        out[0] = d_rho;
-        out[xdir ? 1 : 2] = d_nm;
-        out[xdir ? 2 : 1] = d_tm;
-        out[3] = d_E;
-        out[4] = d_r;
-        double pal = 0.0;
-#pragma unroll
-        for (int f = 0; f < NU5; ++f) {
-            out[f] += al * bq[f];
-            pal += V[f] * bq[f];
-        }
-        pQ = a_nm * P.pQ + a_E * w * P.pQ;
-        const long long src = (xdir ? A.srcx : A.srcy)[s];
-        if (src < 0) {
-            // Dirichlet ghost: its energy depends on Q through the chemical energy rho Y Q
-            const double* row = g.dirU + (size_t)(-src - 1) * (MAXF + 1);
-            pQ += out[3] * row[4];
-        }
-        if (xdir) pax = pal;
-        else pay = pal;
-        double* go = xdir ? A.gx : A.gy;
-#pragma unroll
-        for (int f = 0; f < NU5; ++f) go[(size_t)f * ns + s] = out[f];
-    }
-    const double s0 = block_sum(pax, sh);
-    const double s1 = block_sum(pay, sh);
-    const double s2 = block_sum(pQ, sh);
-    if (threadIdx.x == 0) {
-        A.part[(size_t)blockIdx.x * 4 + 0] = s0;
-        A.part[(size_t)blockIdx.x * 4 + 1] = s1;
-        A.part[(size_t)blockIdx.x * 4 + 2] = s2;
-        A.part[(size_t)blockIdx.x * 4 + 3] = 0.0;
+        mp[f] = ap;
+        mm[f] = am;
     }
 }
 
-// D: interior cells -> lambda of the stage input, source term, RK bookkeeping.
-__global__ __launch_bounds__(AWG) void adj_combine(AdjArgs A) {
+// Reverse of the split at one strip state V: flux Jacobian and the alpha term.
+// out = adjoint of V; pal = d/dalpha part; pQ = d/dQ part.
+__device__ __forceinline__ void split_vjp(const AdjGrid& g, const double (&V)[NU5], bool xdir,
+                                          double al, const double (&mp)[NU5],
+                                          const double (&mm)[NU5], double (&out)[NU5],
+                                          double& pal, double& pQ) {
+    const PGrad P = pgrad(g, V);
+    double a[NU5], bq[NU5];
+#pragma unroll
+    for (int f = 0; f < NU5; ++f) {
+        a[f] = 0.5 * (mp[f] + mm[f]);
+        bq[f] = 0.5 * (mp[f] - mm[f]);
+    }
+    const double rho = V[0], E = V[3], r = V[4];
+    const double ir = 1.0 / rho;
+    // normal velocity w, tangential t; normal momentum index nm, tangential tm
+    const double w = xdir ? P.u : P.v, t = xdir ? P.v : P.u;
+    const double pw = xdir ? P.pm : P.pn, pt = xdir ? P.pn : P.pm;
+    // flux components: mass, normal momentum, tangential momentum, energy, species
+    const double a_mass = a[0], a_nm = a[xdir ? 1 : 2], a_tm = a[xdir ? 2 : 1];
+    const double a_E = a[3], a_r = a[4];
+    const double d_rho = a_nm * (-w * w + P.pr) + a_tm * (-w * t) +
+                         a_E * (-w * (E + P.p) * ir + w * P.pr) + a_r * (-r * w * ir);
+    const double d_nm = a_mass + a_nm * (2.0 * w + pw) + a_tm * t + a_E * ((E + P.p) * ir + w * pw) +
+                        a_r * (r * ir);
+    const double d_tm = a_nm * pt + a_tm * w + a_E * w * pt;
+    const double d_E = a_nm * P.pE + a_E * w * (1.0 + P.pE);
+    const double d_r = a_nm * P.pY + a_E * w * P.pY + a_r * w;
+    out[0] = d_rho;
+    out[xdir ? 1 : 2] = d_nm;
+    out[xdir ? 2 : 1] = d_tm;
+    out[3] = d_E;
+    out[4] = d_r;
+    pal = 0.0;
+#pragma unroll
+    for (int f = 0; f < NU5; ++f) {
+        out[f] += al * bq[f];
+        pal += V[f] * bq[f];
+    }
+    pQ = a_nm * P.pQ + a_E * w * P.pQ;
+}
+
+// Adjoint of one strip position (own or ghost) and its contributions.
+__device__ __forceinline__ void strip_adjoint(const AdjArgs& A, bool xdir, int i, int j, int pos,
+                                              long long src, unsigned fl, const double (&Vc)[NU5],
+                                              double (&out)[NU5], bool add, double& pal,
+                                              double& pQ) {
+    const AdjGrid& g = A.g;
+    double Vs[NU5];
+    if (src >= 0) {
+#pragma unroll
+        for (int f = 0; f < NU5; ++f) Vs[f] = Vc[f];
+        if (fl & 1u) Vs[1] = -Vs[1];
+        if (fl & 2u) Vs[2] = -Vs[2];
+    } else {
+        const double* row = g.dirU + (size_t)(-src - 1) * (MAXF + 1);
+#pragma unroll
+        for (int f = 0; f < NU5; ++f) Vs[f] = row[f];
+    }
+    double mp[NU5], mm[NU5], o[NU5], pa, pq;
+    gather_strip(A, xdir, i, j, pos, mp, mm);
+    split_vjp(g, Vs, xdir, A.alpha[xdir ? 0 : 1], mp, mm, o, pa, pq);
+    if (src < 0) {
+        // Dirichlet ghost: its energy depends on Q through the chemical energy rho Y Q
+        const double* row = g.dirU + (size_t)(-src - 1) * (MAXF + 1);
+        pq += o[3] * row[4];
+    }
+    pal += pa;
+    pQ += pq;
+    if (add) {
+#pragma unroll
+        for (int f = 0; f < NU5; ++f) {
+            double v = o[f];
+            if ((f == 1 && (fl & 1u)) || (f == 2 && (fl & 2u))) v = -v;
+            out[f] += v;
+        }
+    }
+}
+
+// C: per interior cell, the adjoint of the stage input: its own x and y strip
+// positions, the ghost positions that copy or mirror it (and, on the first or
+// last cell of a row or column, the Dirichlet ghosts of that side), the
+// explicit Arrhenius source and the RK bookkeeping. The last workgroup sums
+// the block partials in a fixed order, applies the alpha adjoints at the
+// argmax cells, accumulates theta and, if asked, the loss seed of a state.
+__global__ __launch_bounds__(AWG) void adj_cell(AdjArgs A) {
     __shared__ double sh[8];
+    __shared__ int flag;
     const long long c = (long long)blockIdx.x * AWG + threadIdx.x;
     const AdjGrid& g = A.g;
-    double pQ = 0.0, pEa = 0.0;
+    double pax = 0.0, pay = 0.0, pQ = 0.0, pEa = 0.0;
     if (c < A.n) {
         const int j = (int)(c / g.nx), i = (int)(c - (long long)j * g.nx);
-        const int nxs = xs_n(g), nys = ys_n(g);
-        double out[NU5];
-        const int sxs = j * (g.nx + 6) + (i + 3);
+        double V[NU5], out[NU5];
 #pragma unroll
-        for (int f = 0; f < NU5; ++f) out[f] = A.b * A.lamW[(size_t)f * A.n + c] + A.gx[(size_t)f * nxs + sxs];
-        if (g.twod) {
-            const int sys = (j + 3) * g.nx + i;
-#pragma unroll
-            for (int f = 0; f < NU5; ++f) out[f] += A.gy[(size_t)f * nys + sys];
+        for (int f = 0; f < NU5; ++f) {
+            V[f] = A.V[(size_t)f * A.n + c];
+            out[f] = A.b * A.lamW[(size_t)f * A.n + c];
         }
-        // ghost cells that copy or mirror this cell
-        for (int gq = 0; gq < 6; ++gq) {
-            const int gi = (gq < 3) ? -1 - gq : g.nx + gq - 3;
-            unsigned fl;
-            const long long s = usrc(g, gi, j, fl);
-            if (s != c) continue;
-            const int sx = j * (g.nx + 6) + (gi + 3);
-#pragma unroll
-            for (int f = 0; f < NU5; ++f) {
-                double v = A.gx[(size_t)f * nxs + sx];
-                if ((f == 1 && (fl & 1u)) || (f == 2 && (fl & 2u))) v = -v;
-                out[f] += v;
+        strip_adjoint(A, true, i, j, i + 3, c, 0u, V, out, true, pax, pQ);
+        if (g.twod) strip_adjoint(A, false, i, j, j + 3, c, 0u, V, out, true, pay, pQ);
+        if (i < 3 || i >= g.nx - 3) {
+            for (int gq = 0; gq < 6; ++gq) {
+                const int gi = (gq < 3) ? -1 - gq : g.nx + gq - 3;
+                unsigned fl;
+                const long long s = usrc(g, gi, j, fl);
+                const bool owner = (s == c) || (s < 0 && i == ((gq < 3) ? 0 : g.nx - 1));
+                if (owner) strip_adjoint(A, true, gi, j, gi + 3, s, fl, V, out, s == c, pax, pQ);
             }
         }
-        if (g.twod) {
+        if (g.twod && (j < 3 || j >= g.ny - 3)) {
             for (int gq = 0; gq < 6; ++gq) {
                 const int gj = (gq < 3) ? -1 - gq : g.ny + gq - 3;
                 unsigned fl;
                 const long long s = usrc(g, i, gj, fl);
-                if (s != c) continue;
-                const int sy = (gj + 3) * g.nx + i;
-#pragma unroll
-                for (int f = 0; f < NU5; ++f) {
-                    double v = A.gy[(size_t)f * nys + sy];
-                    if ((f == 1 && (fl & 1u)) || (f == 2 && (fl & 2u))) v = -v;
-                    out[f] += v;
-                }
+                const bool owner = (s == c) || (s < 0 && j == ((gq < 3) ? 0 : g.ny - 1));
+                if (owner) strip_adjoint(A, false, i, gj, gj + 3, s, fl, V, out, s == c, pay, pQ);
             }
         }
         // explicit source S4 = -k r exp(-Ea/T), T = p/(rho R)
-        double V[NU5];
-#pragma unroll
-        for (int f = 0; f < NU5; ++f) V[f] = A.V[(size_t)f * A.n + c];
         const PGrad P = pgrad(g, V);
         const double mu4 = A.b * A.dt * A.lamW[(size_t)4 * A.n + c];
         const double T = P.p / (V[0] * g.R);
@@ -430,7 +462,7 @@ __global__ __launch_bounds__(AWG) void adj_combine(AdjArgs A) {
 #pragma unroll
         for (int f = 0; f < NU5; ++f) out[f] += mu4 * dSdT * dT[f];
         out[4] += mu4 * (-g.k * ex);
-        pQ = mu4 * dSdT * (P.pQ * iRr);
+        pQ += mu4 * dSdT * (P.pQ * iRr);
         pEa = mu4 * (-S / T);
 #pragma unroll
         for (int f = 0; f < NU5; ++f) {
@@ -441,34 +473,32 @@ __global__ __launch_bounds__(AWG) void adj_combine(AdjArgs A) {
             A.acc[(size_t)f * A.n + c] = acc;
         }
     }
-    const double s0 = block_sum(pQ, sh);
-    const double s1 = block_sum(pEa, sh);
+    const double s0 = block_sum(pax, sh);
+    const double s1 = block_sum(pay, sh);
+    const double s2 = block_sum(pQ, sh);
+    const double s3 = block_sum(pEa, sh);
     if (threadIdx.x == 0) {
-        A.part[(size_t)(A.nbc + blockIdx.x) * 4 + 0] = 0.0;
-        A.part[(size_t)(A.nbc + blockIdx.x) * 4 + 1] = 0.0;
-        A.part[(size_t)(A.nbc + blockIdx.x) * 4 + 2] = s0;
-        A.part[(size_t)(A.nbc + blockIdx.x) * 4 + 3] = s1;
+        A.part[(size_t)blockIdx.x * 4 + 0] = s0;
+        A.part[(size_t)blockIdx.x * 4 + 1] = s1;
+        A.part[(size_t)blockIdx.x * 4 + 2] = s2;
+        A.part[(size_t)blockIdx.x * 4 + 3] = s3;
     }
-}
-
-// E: one workgroup; deterministic sums, alpha adjoints at the argmax cells.
-__global__ void adj_finish(AdjArgs A) {
+    if (!last_block(A.cnt, gridDim.x, &flag)) return;
     if (threadIdx.x != 0) return;
     double sax = 0.0, say = 0.0, sQ = 0.0, sEa = 0.0;
-    for (int q = 0; q < A.nbc + A.nbd; ++q) {
+    for (int q = 0; q < A.nbd; ++q) {
         sax += A.part[(size_t)q * 4 + 0];
         say += A.part[(size_t)q * 4 + 1];
         sQ += A.part[(size_t)q * 4 + 2];
         sEa += A.part[(size_t)q * 4 + 3];
     }
-    const AdjGrid& g = A.g;
     for (int d = 0; d < (g.twod ? 2 : 1); ++d) {
         const double mua = d == 0 ? sax : say;
-        const long long c = A.argm[d];
-        if (c < 0 || c >= A.n) continue;   // no cell attained the maximum (cannot happen for finite data)
+        const long long ca = A.argm[d];
+        if (ca < 0 || ca >= A.n) continue;   // no cell attained the maximum (cannot happen for finite data)
         double V[NU5];
 #pragma unroll
-        for (int f = 0; f < NU5; ++f) V[f] = A.V[(size_t)f * A.n + c];
+        for (int f = 0; f < NU5; ++f) V[f] = A.V[(size_t)f * A.n + ca];
         const PGrad P = pgrad(g, V);
         const double rho = V[0];
         const double cs = sqrt(g.gamma * P.p / rho);
@@ -483,17 +513,28 @@ __global__ void adj_finish(AdjArgs A) {
         gr[4] = kc * P.pY;
 #pragma unroll
         for (int f = 0; f < NU5; ++f) {
-            A.lamOut[(size_t)f * A.n + c] += mua * gr[f];
-            if (A.add_out) A.acc[(size_t)f * A.n + c] += mua * gr[f];
+            A.lamOut[(size_t)f * A.n + ca] += mua * gr[f];
+            if (A.add_out) A.acc[(size_t)f * A.n + ca] += mua * gr[f];
         }
         sQ += mua * kc * P.pQ;
     }
     A.theta[0] += sQ;
     A.theta[1] += sEa;
-    A.amax[0] = 0ull;
-    A.amax[1] = 0ull;
-    A.argm[0] = 0x7fffffff;
-    A.argm[1] = 0x7fffffff;
+    if (A.seedU) {
+        // loss seed of the step start state: acc += dt sum_q w_q dp/dU at the probes
+        for (int q = 0; q < A.np; ++q) {
+            double V[NU5];
+            for (int f = 0; f < NU5; ++f) V[f] = A.seedU[(size_t)f * A.n + A.pc[q]];
+            const PGrad P = pgrad(g, V);
+            const double s = A.dt * A.pw[q];
+            A.acc[(size_t)0 * A.n + A.pc[q]] += s * P.pr;
+            A.acc[(size_t)1 * A.n + A.pc[q]] += s * P.pm;
+            A.acc[(size_t)2 * A.n + A.pc[q]] += s * P.pn;
+            A.acc[(size_t)3 * A.n + A.pc[q]] += s * P.pE;
+            A.acc[(size_t)4 * A.n + A.pc[q]] += s * P.pY;
+            A.theta[0] += s * P.pQ;
+        }
+    }
 }
 
 // Loss accumulation of the forward pass: loss += dt sum_q w_q p(U[cell_q]).
@@ -556,32 +597,17 @@ __global__ void adj_chain_sum(const double* part, int nb, double* theta) {
     theta[0] += s;
 }
 
-__global__ void adj_reset(AdjArgs A) {
-    if (threadIdx.x == 0) {
-        A.amax[0] = 0ull;
-        A.amax[1] = 0ull;
-        A.argm[0] = 0x7fffffff;
-        A.argm[1] = 0x7fffffff;
-    }
-}
-
 // ------------------------------------------------------------------ launchers
-hipError_t adj_stage(const AdjArgs& A, hipStream_t s) {
-    const int nc = (int)((A.n + AWG - 1) / AWG);
-    const int ns = xs_n(A.g) + ys_n(A.g);
-    const int ni = (A.g.nx + 1) * A.g.ny + (A.g.twod ? A.g.nx * (A.g.ny + 1) : 0);
-    adj_alpha<<<nc, AWG, 0, s>>>(A);
-    adj_argmax<<<nc, AWG, 0, s>>>(A);
-    adj_prep<<<(ns + AWG - 1) / AWG, AWG, 0, s>>>(A);
-    adj_iface<<<(ni + AWG - 1) / AWG, AWG, 0, s>>>(A);
-    adj_gather<<<(ns + AWG - 1) / AWG, AWG, 0, s>>>(A);
-    adj_combine<<<nc, AWG, 0, s>>>(A);
-    adj_finish<<<1, 64, 0, s>>>(A);
+hipError_t adj_alpha_launch(const AlphaArgs& P, hipStream_t s) {
+    if (P.nsteps <= 0) return hipSuccess;
+    adj_alpha<<<dim3(P.nbd, 3 * P.nsteps), AWG, 0, s>>>(P);
     return hipGetLastError();
 }
 
-hipError_t adj_reset_launch(const AdjArgs& A, hipStream_t s) {
-    adj_reset<<<1, 64, 0, s>>>(A);
+hipError_t adj_stage(const AdjArgs& A, hipStream_t s) {
+    const int ni = (A.g.nx + 1) * A.g.ny + (A.g.twod ? A.g.nx * (A.g.ny + 1) : 0);
+    adj_iface<<<(ni + AWG - 1) / AWG, AWG, 0, s>>>(A);
+    adj_cell<<<A.nbd, AWG, 0, s>>>(A);
     return hipGetLastError();
 }
 
@@ -604,13 +630,6 @@ hipError_t adj_chain_launch(const AdjGrid& g, const double* W, const double* lam
     adj_chain_ic<<<nb, AWG, 0, s>>>(g, W, lam, n, gW, part);
     adj_chain_sum<<<1, 64, 0, s>>>(part, nb, theta);
     return hipGetLastError();
-}
-
-int adj_partial_blocks(const AdjGrid& g, long long n, int* nbc, int* nbd) {
-    const int ns = (g.nx + 6) * g.ny + (g.twod ? g.nx * (g.ny + 6) : 0);
-    *nbc = (ns + AWG - 1) / AWG;
-    *nbd = (int)((n + AWG - 1) / AWG);
-    return *nbc + *nbd;
 }
 
 }  // namespace janc

@@ -618,23 +618,20 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     ag.Ea = ph->Ea;
     ag.k = ph->k;
     ag.dirU = P->ddir;
-    int nbc = 0, nbd = 0;
-    const int nparts = adj_partial_blocks(ag, n, &nbc, &nbd);
-    const long long nxs = (long long)(g->nx + 6) * g->ny;
-    const long long nys = ag.twod ? (long long)g->nx * (g->ny + 6) : 0;
+    const int nbd = (int)((n + 255) / 256);          // cell blocks of the adjoint kernels
     const long long nix = (long long)(g->nx + 1) * g->ny;
     const long long niy = ag.twod ? (long long)g->nx * (g->ny + 1) : 0;
     const long long n5 = 5 * n;
+    const int nsl = 3 * K;                            // stage inputs of one segment
     // workspace layout (doubles)
     struct Seg { size_t off, len; };
     size_t tot = 0;
     auto take = [&](size_t len) { Seg r{tot, len}; tot += (len + 31) & ~(size_t)31; return r; };
     const Seg sCk = take((size_t)nseg * n5), sS0 = take((size_t)(K + 1) * n5), sS1 = take((size_t)K * n5),
               sS2 = take((size_t)K * n5), sLam = take(n5), sLA = take(n5), sLB = take(n5), sAcc = take(n5),
-              sT0 = take(n), sT1 = take(n), sVx = take(5 * nxs), sFpx = take(5 * nxs), sFmx = take(5 * nxs),
-              sGx = take(5 * nxs), sVy = take(5 * nys), sFpy = take(5 * nys), sFmy = take(5 * nys),
-              sGy = take(5 * nys), sSx = take(nxs), sSy = take(nys), sCx = take(50 * nix),
-              sCy = take(50 * niy), sPart = take(4 * (size_t)std::max(nparts, (int)((n + 255) / 256)) + 8),
+              sT0 = take(n), sT1 = take(n), sCx = take(50 * nix), sCy = take(50 * niy),
+              sPart = take(4 * (size_t)nbd + 8), sApart = take((size_t)nsl * nbd * 4),
+              sAlpha = take(2 * (size_t)nsl), sArgm = take((size_t)nsl), sCnt = take((size_t)nsl / 2 + 2),
               sMisc = take(16), sPc = take(np + 1), sPw = take(np + 1);
     if (tot > c->adj_doubles) {
         if (c->adj_mem) hipFree(c->adj_mem);
@@ -665,6 +662,8 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     HIPCHK(c, hipMemsetAsync(loss, 0, sizeof(double), s), "memset");
     HIPCHK(c, hipMemsetAsync(theta, 0, 2 * sizeof(double), s), "memset");
     HIPCHK(c, hipMemsetAsync(lam, 0, sizeof(double) * n5, s), "memset");
+    unsigned* cnt = (unsigned*)at(sCnt);               // [nsl] alpha slices, [nsl] the cell kernel
+    HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(unsigned) * (nsl + 1), s), "memset");
     // U0 from the primitives (the Q dependence of E0 is chained at the end)
     HIPCHK(c, launch_prim_to_cons(ONESTEP, 0, nullptr, ph->gamma, ph->R, ph->Q, n, W0, ck, T0, n, n, s),
            "init_state");
@@ -712,17 +711,29 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     A.g = ag;
     A.n = n;
     A.dt = dt;
-    A.Vx = at(sVx); A.Fpx = at(sFpx); A.Fmx = at(sFmx); A.gx = at(sGx);
-    A.Vy = at(sVy); A.Fpy = at(sFpy); A.Fmy = at(sFmy); A.gy = at(sGy);
-    A.srcx = (long long*)at(sSx); A.srcy = (long long*)at(sSy);
-    A.cx = at(sCx); A.cy = at(sCy);
-    A.amax = (unsigned long long*)(misc + 4);
-    A.argm = (int*)(misc + 6);
+    A.cx = at(sCx);
+    A.cy = at(sCy);
     A.part = at(sPart);
-    A.nbc = nbc;
+    A.cnt = cnt + nsl;
     A.nbd = nbd;
     A.theta = theta;
-    HIPCHK(c, adj_reset_launch(A, s), "adjoint reset");
+    A.pc = dpc;
+    A.pw = dpw;
+    A.np = np;
+    double* alpha = at(sAlpha);
+    int* argm = (int*)at(sArgm);
+    AlphaArgs AP{};
+    AP.g = ag;
+    AP.n = n;
+    AP.base[0] = S0;
+    AP.base[1] = S1;
+    AP.base[2] = S2;
+    AP.step_stride = n5;
+    AP.nbd = nbd;
+    AP.part = at(sApart);
+    AP.cnt = cnt;
+    AP.alpha = alpha;
+    AP.argm = argm;
     HIPCHK(c, adj_seed_launch(ag, cur, n, dpc, dpw, np, dt, lam, theta, s), "seed");
     for (int sg = nseg - 1; sg >= 0; --sg) {
         const int n0 = sg * K, n1 = std::min(N, n0 + K), m1 = n1 - n0;
@@ -741,22 +752,27 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
             HIPCHK(c, stage(1, u0, u0, S1 + (size_t)m * n5), "recompute stage");
             HIPCHK(c, stage(2, u0, S1 + (size_t)m * n5, S2 + (size_t)m * n5), "recompute stage");
         }
+        // alpha and its argmax of all 3 m1 stage inputs
+        AP.nsteps = m1;
+        HIPCHK(c, adj_alpha_launch(AP, s), "adjoint alpha");
         for (int m = m1 - 1; m >= 0; --m) {
             AdjArgs a3 = A;   // stage 3: W = U/3 + 2/3 (V + dt L(V)), V = U^(2)
             a3.V = S2 + (size_t)m * n5; a3.lamW = lam; a3.lamOut = lA; a3.acc = acc;
             a3.b = 2.0 / 3.0; a3.a = 1.0 / 3.0; a3.init_acc = 1; a3.add_out = 0;
+            a3.alpha = alpha + 2 * (3 * m + 2); a3.argm = argm + 2 * (3 * m + 2);
             HIPCHK(c, adj_stage(a3, s), "adjoint stage 3");
             AdjArgs a2 = A;   // stage 2: W = 3/4 U + 1/4 (V + dt L(V)), V = U^(1)
             a2.V = S1 + (size_t)m * n5; a2.lamW = lA; a2.lamOut = lB; a2.acc = acc;
             a2.b = 0.25; a2.a = 0.75; a2.init_acc = 0; a2.add_out = 0;
+            a2.alpha = alpha + 2 * (3 * m + 1); a2.argm = argm + 2 * (3 * m + 1);
             HIPCHK(c, adj_stage(a2, s), "adjoint stage 2");
-            AdjArgs a1 = A;   // stage 1: W = V + dt L(V), V = U^n
+            AdjArgs a1 = A;   // stage 1: W = V + dt L(V), V = U^n; then the loss seed of U^n
             a1.V = S0 + (size_t)m * n5; a1.lamW = lB; a1.lamOut = lA; a1.acc = acc;
             a1.b = 1.0; a1.a = 0.0; a1.init_acc = 0; a1.add_out = 1;
+            a1.alpha = alpha + 2 * (3 * m); a1.argm = argm + 2 * (3 * m);
+            a1.seedU = (n0 + m >= 1) ? S0 + (size_t)m * n5 : nullptr;
             HIPCHK(c, adj_stage(a1, s), "adjoint stage 1");
             std::swap(lam, acc);
-            if (n0 + m >= 1)
-                HIPCHK(c, adj_seed_launch(ag, S0 + (size_t)m * n5, n, dpc, dpw, np, dt, lam, theta, s), "seed");
         }
     }
     // chain dL/dU0 to the primitives; E0 = p/(gamma-1) + rho |u|^2/2 + rho Y Q adds to dL/dQ

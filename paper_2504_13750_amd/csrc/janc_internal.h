@@ -145,18 +145,36 @@ struct AdjArgs {
     double* acc;              // adjoint of the step start U^n [5][n]
     double b, a, dt;
     int init_acc, add_out;
-    double *Vx, *Fpx, *Fmx, *Vy, *Fpy, *Fmy;
-    long long *srcx, *srcy;
-    double *cx, *cy, *gx, *gy;
-    unsigned long long* amax; // [2]
-    int* argm;                // [2]
-    double* part;             // [nblocks][4]
-    int nbc, nbd;             // partial blocks used by C and D
+    double *cx, *cy;          // reverse WENO5 weights per interface [5][10][interfaces]
+    const double* alpha;      // [2] alpha_x, alpha_y of the stage input
+    const int* argm;          // [2] lowest cell attaining them
+    double* part;             // [nbd][4] block partials
+    unsigned* cnt;            // completion counter of the stage's cell kernel
+    int nbd;                  // cell blocks
     double* theta;            // [2]: dL/dQ, dL/dEa
+    const double* seedU;      // state whose probe loss seeds acc after this stage (or null)
+    const int* pc;
+    const double* pw;
+    int np;
 };
 
+// Alpha maxima and argmax of every stage input of a run of steps (one launch):
+// slice z = 3 m + (stage - 1) reads base[stage - 1] + m * step_stride.
+struct AlphaArgs {
+    AdjGrid g;
+    long long n;
+    const double* base[3];
+    long long step_stride;
+    int nsteps;
+    int nbd;
+    double* part;             // [slices][nbd][4]
+    unsigned* cnt;            // [slices]
+    double* alpha;            // [slices][2]
+    int* argm;                // [slices][2]
+};
+
+hipError_t adj_alpha_launch(const AlphaArgs& P, hipStream_t s);
 hipError_t adj_stage(const AdjArgs& A, hipStream_t s);
-hipError_t adj_reset_launch(const AdjArgs& A, hipStream_t s);
 hipError_t adj_loss_launch(const AdjGrid& g, const double* U, long long n, const int* pc,
                            const double* pw, int np, double dt, double* loss, hipStream_t s);
 hipError_t adj_seed_launch(const AdjGrid& g, const double* U, long long n, const int* pc,
@@ -164,6 +182,5 @@ hipError_t adj_seed_launch(const AdjGrid& g, const double* U, long long n, const
                            hipStream_t s);
 hipError_t adj_chain_launch(const AdjGrid& g, const double* W, const double* lam, long long n,
                             double* gW, double* part, double* theta, hipStream_t s);
-int adj_partial_blocks(const AdjGrid& g, long long n, int* nbc, int* nbd);
 
 }  // namespace janc

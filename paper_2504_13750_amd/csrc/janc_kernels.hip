@@ -23,18 +23,40 @@
 namespace janc {
 
 // ------------------------------------------------------------------ the stage tile
+// Points of a tile: the TX x TY owned positions first (point tid is thread tid's
+// own cell), then the x halo (3 columns each side of every row) and, for 2-D
+// tiles, the y halo (3 rows below and above every column).
 template <int TX, int TY>
 struct Geom {
     static constexpr bool TWO = TY > 1;
-    static constexpr int GY = TWO ? 3 : 0;
-    static constexpr int PW = TX + 6, PH = TY + 2 * GY, NP = PW * PH, NPT = (NP + WG - 1) / WG;
-    static constexpr int NXS = PW * TY;
-    static constexpr int NYS = TWO ? TX * (TY + 6) : 0;
-    static constexpr int NIX = (TX + 1) * TY;
-    static constexpr int NIY = TWO ? TX * (TY + 1) : 0;
     static constexpr int NC = TX * TY;
-    // LDS doubles: fpx, fmx, fpy, fmy, fhx, fhy, T of cells, explicit source, scratch
-    static constexpr int LDS = 2 * NXS + 2 * NYS + NIX + NIY + 2 * NC + 16;
+    static constexpr int NHX = 6 * TY, NHY = TWO ? 6 * TX : 0;
+    static constexpr int NP = NC + NHX + NHY, NPT = (NP + WG - 1) / WG;
+    static constexpr int PW = TX + 6;
+    static constexpr int NXS = PW * TY;                 // x split fluxes, row-major, 3 halo columns
+    static constexpr int NYS = TWO ? TX * (TY + 6) : 0; // y split fluxes, 3 halo rows
+    static constexpr int NIX = (TX + 1) * TY;           // x interfaces
+    static constexpr int NIY = TWO ? TX * (TY + 1) : 0; // y interfaces
+    static constexpr int NTASK = 2 * (NIX + NIY);       // one WENO5 reconstruction each
+    // LDS doubles: F+/F- and G+/G-, the four one-sided interface values, scratch
+    static constexpr int LDS = 2 * NXS + 2 * NYS + 2 * NIX + 2 * NIY + 16;
+
+    // tile-local position (li, lj) of point p
+    __device__ static void point(int p, int& li, int& lj) {
+        if (p < NC) {
+            lj = p / TX;
+            li = p - lj * TX;
+        } else if (p < NC + NHX) {
+            const int h = p - NC, side = h / (3 * TY), r = h - side * 3 * TY;
+            lj = r / 3;
+            li = side ? TX + (r - lj * 3) : (r - lj * 3) - 3;
+        } else {
+            const int h = p - NC - NHX, side = h / (3 * TX), r = h - side * 3 * TX;
+            const int row = r / TX;
+            li = r - row * TX;
+            lj = side ? TY + row : row - 3;
+        }
+    }
 };
 
 template <int M, int NU, int TX, int TY>
@@ -45,11 +67,11 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
     double* fmx = fpx + G::NXS;
     double* fpy = fmx + G::NXS;
     double* fmy = fpy + G::NYS;
-    double* fhx = fmy + G::NYS;
-    double* fhy = fhx + G::NIX;
-    double* tcell = fhy + G::NIY;
-    double* scell = tcell + G::NC;
-    double* scratch = scell + G::NC;
+    double* hxp = fmy + G::NYS;      // WENO5 of F+ at x interfaces
+    double* hxm = hxp + G::NIX;      // WENO5 of F- at x interfaces
+    double* hyp = hxm + G::NIX;
+    double* hym = hyp + G::NIY;
+    double* scratch = hym + G::NIY;
 
     const int tid = threadIdx.x;
     const DevBlock B = a.blk[tile.block];
@@ -70,18 +92,23 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
     double ur[G::NPT][NU];
     double vxr[G::NPT], vyr[G::NPT], pr[G::NPT];
     bool needx[G::NPT], needy[G::NPT];
+    int xoff[G::NPT], yoff[G::NPT];
+    double Town = 0.0;
 #pragma unroll
     for (int q = 0; q < G::NPT; ++q) {
         const int p = tid + q * WG;
         needx[q] = needy[q] = false;
+        xoff[q] = yoff[q] = 0;
         vxr[q] = vyr[q] = pr[q] = 0.0;
 #pragma unroll
         for (int f = 0; f < NU; ++f) ur[q][f] = 0.0;
         if (p < G::NP) {
-            const int pj = p / G::PW, pi = p - pj * G::PW;
-            const int li = pi - 3, lj = pj - G::GY;
+            int li, lj;
+            G::point(p, li, lj);
             needx[q] = (lj >= 0 && lj < th) && (li >= -3 && li < tw + 3);
             needy[q] = G::TWO && (li >= 0 && li < tw) && (lj >= -3 && lj < th + 3);
+            xoff[q] = lj * G::PW + li + 3;
+            yoff[q] = (lj + 3) * TX + li;
             if (needx[q] || needy[q]) {
                 const int bi = tile.x0 + li, bj = tile.y0 + lj;
                 long long src;
@@ -93,81 +120,99 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
                 double T;
                 fetch<NU>(a, src, fl, a.Uin, a.Tin, ur[q], T);
                 halo_prims<M, NU>(ur[q], T, D, cmech(a.mech), vxr[q], vyr[q], pr[q]);
-                if (li >= 0 && li < TX && lj >= 0 && lj < TY) {
-                    tcell[lj * TX + li] = T;
-                    if constexpr (M == ONESTEP) {
-                        const double Tc = pr[q] / (ur[q][0] * D.R);
-                        scell[lj * TX + li] = -D.k * ur[q][4] * exp(-D.Ea / Tc);
-                    }
-                }
+                if (q == 0) Town = T;
             }
         }
     }
 
-    // owned cell
+    // owned cell: point tid, held in ur[0]
     const int oli = tid % TX, olj = tid / TX;
     const int obi = tile.x0 + oli, obj = tile.y0 + olj;
     const bool own = (oli < tw) && (olj < th) && !ring_at(B, obi, obj);
     const long long oc = B.offset + (long long)obj * B.nx + obi;
+    double src_e = 0.0;   // explicit source of the one-step model (Sec. 4.3)
+    if constexpr (M == ONESTEP) {
+        if (own) {
+            const double Tc = pr[0] / (ur[0][0] * D.R);
+            src_e = -D.k * ur[0][4] * exp(-D.Ea / Tc);
+        }
+    }
     double unew[NU];
 
     // ---------------- phase 1: per component split fluxes, WENO5, RK update
 #pragma unroll
     for (int f = 0; f < NU; ++f) {
+        // stage input U^(0) of the owned cell, issued ahead of the reconstruction
+        double u0 = 0.0;
+        if (own) u0 = (stage == 1) ? ur[0][f] : a.U0[(size_t)f * a.pool + oc];
 #pragma unroll
         for (int q = 0; q < G::NPT; ++q) {
-            const int p = tid + q * WG;
-            const int pj = p / G::PW, pi = p - pj * G::PW;
             const double uf = ur[q][f];
             if (needx[q]) {
                 double F = uf * vxr[q];
                 if (f == 1) F += pr[q];
                 if (f == 3) F = (uf + pr[q]) * vxr[q];
-                const int xi = (pj - G::GY) * G::PW + pi;
-                fpx[xi] = 0.5 * (F + ax * uf);
-                fmx[xi] = 0.5 * (F - ax * uf);
+                fpx[xoff[q]] = 0.5 * (F + ax * uf);
+                fmx[xoff[q]] = 0.5 * (F - ax * uf);
             }
             if constexpr (G::TWO) {
                 if (needy[q]) {
                     double Gf = uf * vyr[q];
                     if (f == 2) Gf += pr[q];
                     if (f == 3) Gf = (uf + pr[q]) * vyr[q];
-                    const int yi = pj * TX + (pi - 3);
-                    fpy[yi] = 0.5 * (Gf + ay * uf);
-                    fmy[yi] = 0.5 * (Gf - ay * uf);
+                    fpy[yoff[q]] = 0.5 * (Gf + ay * uf);
+                    fmy[yoff[q]] = 0.5 * (Gf - ay * uf);
                 }
             }
         }
         __syncthreads();
-        for (int r = tid; r < G::NIX; r += WG) {
-            const int lj = r / (TX + 1), k = r - lj * (TX + 1);
-            if (lj < th && k <= tw) {
-                const double* P = fpx + lj * G::PW + k;
-                const double* Mn = fmx + lj * G::PW + k;
-                fhx[r] = weno5(P[0], P[1], P[2], P[3], P[4]) + weno5(Mn[5], Mn[4], Mn[3], Mn[2], Mn[1]);
+        // one-sided WENO5 reconstructions, spread evenly over the workgroup:
+        // task = (direction, side, interface); the F- side reads its stencil mirrored
+        for (int t = tid; t < G::NTASK; t += WG) {
+            int r = t;
+            const bool isy = G::TWO && r >= 2 * G::NIX;
+            if (isy) r -= 2 * G::NIX;
+            const int n = isy ? G::NIY : G::NIX;
+            const bool minus = r >= n;
+            if (minus) r -= n;
+            int row, col, stride, boff;
+            bool valid;
+            if (!isy) {
+                row = r / (TX + 1);
+                col = r - row * (TX + 1);
+                valid = row < th && col <= tw;
+                boff = row * G::PW + col;
+                stride = 1;
+            } else {
+                row = r / TX;
+                col = r - row * TX;
+                valid = col < tw && row <= th;
+                boff = row * TX + col;
+                stride = TX;
             }
-        }
-        if constexpr (G::TWO) {
-            for (int r = tid; r < G::NIY; r += WG) {
-                const int k = r / TX, li = r - k * TX;
-                if (li < tw && k <= th) {
-                    const double* P = fpy + k * TX + li;
-                    const double* Mn = fmy + k * TX + li;
-                    fhy[r] = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX]) +
-                             weno5(Mn[5 * TX], Mn[4 * TX], Mn[3 * TX], Mn[2 * TX], Mn[TX]);
-                }
+            const double* base = isy ? (minus ? fmy : fpy) : (minus ? fmx : fpx);
+            base += boff;
+            if (minus) {
+                base += 5 * stride;
+                stride = -stride;
             }
+            double* out = isy ? (minus ? hym : hyp) : (minus ? hxm : hxp);
+            if (valid)
+                out[r] = weno5(base[0], base[stride], base[2 * stride], base[3 * stride],
+                               base[4 * stride]);
         }
         __syncthreads();
         if (own) {
-            double L = -(fhx[olj * (TX + 1) + oli + 1] - fhx[olj * (TX + 1) + oli]) * idx;
-            if constexpr (G::TWO) L -= (fhy[(olj + 1) * TX + oli] - fhy[olj * TX + oli]) * idy;
-            if constexpr (M == ONESTEP) {
-                if (f == 4) L += scell[olj * TX + oli];
+            const int rx = olj * (TX + 1) + oli;
+            double L = -((hxp[rx + 1] + hxm[rx + 1]) - (hxp[rx] + hxm[rx])) * idx;
+            if constexpr (G::TWO) {
+                const int ry = olj * TX + oli;
+                L -= ((hyp[ry + TX] + hym[ry + TX]) - (hyp[ry] + hym[ry])) * idy;
             }
-            const double u0 = a.U0[(size_t)f * a.pool + oc];
-            const double us = a.Uin[(size_t)f * a.pool + oc];
-            const double un = rk_combine(stage, u0, us, L, dt);
+            if constexpr (M == ONESTEP) {
+                if (f == 4) L += src_e;
+            }
+            const double un = rk_combine(stage, u0, ur[0][f], L, dt);
             a.Uout[(size_t)f * a.pool + oc] = un;
             unew[f] = un;
         }
@@ -177,7 +222,7 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
     double sx = 0.0, sy = 0.0, sc = 0.0;
     if (own) {
         double T, c, vx, vy;
-        const unsigned st = owner_state<M, NU>(unew, tcell[olj * TX + oli], D, cmech(a.mech), T, c, vx, vy);
+        const unsigned st = owner_state<M, NU>(unew, Town, D, cmech(a.mech), T, c, vx, vy);
         a.Tout[oc] = T;
         if (st) atomicOr(a.status, st);
         const bool skip = (stage == 3) && B.fine_child &&
