@@ -55,7 +55,7 @@ enum {
     JANC_MODEL_DETAILED = 2  /* NASA-7 + mass-action mechanism, point-implicit (Eq. 4.2-4.9, 4.12) */
 };
 
-enum { JANC_MAX_FIELDS = 16, JANC_MAX_LEVELS = 8 };
+enum { JANC_MAX_FIELDS = 16, JANC_MAX_LEVELS = 8, JANC_MAX_PROBES = 8 };
 
 /* Detailed mechanism (host arrays, copied at janc_create), SI units:
  * M [ns] kg/mol; nasa [ns][7] single-range NASA-7 coefficients a0..a6
@@ -200,7 +200,9 @@ janc_status janc_profile_step(janc_ctx *ctx, janc_plan *plan, const janc_time *t
  * checkpointed every ckpt_every steps and recomputed inside each segment.
  * Outputs (device): loss[1], dL_dW0 [5][ny][nx], dL_dtheta[2] = {dL/dQ, dL/dEa}
  * (Q enters through the equation of state and the initial energy). probe_cell
- * and probe_w are host arrays of nprobes entries. */
+ * and probe_w are host arrays of nprobes (0 .. JANC_MAX_PROBES) entries; a probe
+ * cell out of range, a count out of range, dt_fixed <= 0, t_end > 0 or a model
+ * other than the one-step model return JANC_EINVAL. */
 janc_status janc_adjoint(janc_ctx *ctx, const janc_grid *grid, const janc_physics *phys,
                          const janc_time *time, const double *W0, int nsteps, int ckpt_every,
                          int nprobes, const int *probe_cell, const double *probe_w,

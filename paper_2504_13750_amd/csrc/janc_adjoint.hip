@@ -158,20 +158,6 @@ __device__ __forceinline__ int block_min(int v, int* sh) {
     return r;
 }
 
-// Completion count of a launch: true in the one workgroup that finishes last,
-// after which it sees every other workgroup's stores. Each thread releases its
-// own stores at device scope before the count; the counter is reset for reuse.
-__device__ __forceinline__ bool last_block(unsigned* cnt, unsigned nblocks, int* flag) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) *flag = (atomicAdd(cnt, 1u) == nblocks - 1) ? 1 : 0;
-    __syncthreads();
-    if (!*flag) return false;
-    __threadfence();
-    if (threadIdx.x == 0) *cnt = 0u;
-    return true;
-}
-
 // Wave speeds of a cell of state V as the forward reductions compute them.
 __device__ __forceinline__ void cell_speeds_of(const AdjGrid& g, const double* V, long long n,
                                                long long c, double& sx, double& sy) {
@@ -189,11 +175,10 @@ __device__ __forceinline__ void cell_speeds_of(const AdjGrid& g, const double* V
 }
 
 // A: alpha_x, alpha_y of every stage input of a run of steps and the lowest
-// cell attaining each (block maxima, then the last workgroup of the slice).
+// cell attaining each: block maxima here, one workgroup per slice below.
 __global__ __launch_bounds__(AWG) void adj_alpha(AlphaArgs P) {
     __shared__ double sh[8];
     __shared__ int ish[8];
-    __shared__ int flag;
     const int z = blockIdx.y;
     const double* V = P.base[z % 3] + (size_t)(z / 3) * P.step_stride;
     const long long c = (long long)blockIdx.x * AWG + threadIdx.x;
@@ -202,14 +187,20 @@ __global__ __launch_bounds__(AWG) void adj_alpha(AlphaArgs P) {
     const double mx = block_max(sx, sh), my = block_max(sy, sh);
     const int ix = block_min((c < P.n && sx == mx) ? (int)c : 0x7fffffff, ish);
     const int iy = block_min((c < P.n && sy == my) ? (int)c : 0x7fffffff, ish);
-    double* part = P.part + (size_t)z * P.nbd * 4;
     if (threadIdx.x == 0) {
-        part[(size_t)blockIdx.x * 4 + 0] = mx;
-        part[(size_t)blockIdx.x * 4 + 1] = my;
-        part[(size_t)blockIdx.x * 4 + 2] = (double)ix;
-        part[(size_t)blockIdx.x * 4 + 3] = (double)iy;
+        double* part = P.part + ((size_t)z * P.nbd + blockIdx.x) * 4;
+        part[0] = mx;
+        part[1] = my;
+        part[2] = (double)ix;
+        part[3] = (double)iy;
     }
-    if (!last_block(P.cnt + z, gridDim.x, &flag)) return;
+}
+
+__global__ __launch_bounds__(AWG) void adj_alpha_reduce(AlphaArgs P) {
+    __shared__ double sh[8];
+    __shared__ int ish[8];
+    const int z = blockIdx.x;
+    const double* part = P.part + (size_t)z * P.nbd * 4;
     double bx = -1.0, by = -1.0;
     for (int q = threadIdx.x; q < P.nbd; q += AWG) {
         bx = fmax(bx, part[(size_t)q * 4 + 0]);
@@ -413,43 +404,61 @@ __device__ __forceinline__ void strip_adjoint(const AdjArgs& A, bool xdir, int i
 // C: per interior cell, the adjoint of the stage input: its own x and y strip
 // positions, the ghost positions that copy or mirror it (and, on the first or
 // last cell of a row or column, the Dirichlet ghosts of that side), the
-// explicit Arrhenius source and the RK bookkeeping. The last workgroup sums
-// the block partials in a fixed order, applies the alpha adjoints at the
-// argmax cells, accumulates theta and, if asked, the loss seed of a state.
+// explicit Arrhenius source and the RK bookkeeping; per-block partials of the
+// alpha, Q and Ea adjoints. Two threads per cell: the first half of the
+// workgroup takes the x sweep, the second half the y sweep, and the y part
+// reaches the cell's thread through LDS.
+constexpr int CPB = AWG / 2;
+
 __global__ __launch_bounds__(AWG) void adj_cell(AdjArgs A) {
     __shared__ double sh[8];
-    __shared__ int flag;
-    const long long c = (long long)blockIdx.x * AWG + threadIdx.x;
+    __shared__ double ysum[NU5][CPB];
+    const int lc = threadIdx.x % CPB;
+    const bool ydir = threadIdx.x >= CPB;
+    const long long c = (long long)blockIdx.x * CPB + lc;
     const AdjGrid& g = A.g;
     double pax = 0.0, pay = 0.0, pQ = 0.0, pEa = 0.0;
-    if (c < A.n) {
-        const int j = (int)(c / g.nx), i = (int)(c - (long long)j * g.nx);
-        double V[NU5], out[NU5];
+    double V[NU5], out[NU5];
 #pragma unroll
-        for (int f = 0; f < NU5; ++f) {
-            V[f] = A.V[(size_t)f * A.n + c];
-            out[f] = A.b * A.lamW[(size_t)f * A.n + c];
-        }
-        strip_adjoint(A, true, i, j, i + 3, c, 0u, V, out, true, pax, pQ);
-        if (g.twod) strip_adjoint(A, false, i, j, j + 3, c, 0u, V, out, true, pay, pQ);
-        if (i < 3 || i >= g.nx - 3) {
-            for (int gq = 0; gq < 6; ++gq) {
-                const int gi = (gq < 3) ? -1 - gq : g.nx + gq - 3;
-                unsigned fl;
-                const long long s = usrc(g, gi, j, fl);
-                const bool owner = (s == c) || (s < 0 && i == ((gq < 3) ? 0 : g.nx - 1));
-                if (owner) strip_adjoint(A, true, gi, j, gi + 3, s, fl, V, out, s == c, pax, pQ);
+    for (int f = 0; f < NU5; ++f) out[f] = 0.0;
+    const int j = (int)(c / g.nx), i = (int)(c - (long long)j * g.nx);
+    if (c < A.n) {
+#pragma unroll
+        for (int f = 0; f < NU5; ++f) V[f] = A.V[(size_t)f * A.n + c];
+        if (!ydir) {
+#pragma unroll
+            for (int f = 0; f < NU5; ++f) out[f] = A.b * A.lamW[(size_t)f * A.n + c];
+            strip_adjoint(A, true, i, j, i + 3, c, 0u, V, out, true, pax, pQ);
+            if (i < 3 || i >= g.nx - 3) {
+                for (int gq = 0; gq < 6; ++gq) {
+                    const int gi = (gq < 3) ? -1 - gq : g.nx + gq - 3;
+                    unsigned fl;
+                    const long long s = usrc(g, gi, j, fl);
+                    const bool owner = (s == c) || (s < 0 && i == ((gq < 3) ? 0 : g.nx - 1));
+                    if (owner) strip_adjoint(A, true, gi, j, gi + 3, s, fl, V, out, s == c, pax, pQ);
+                }
+            }
+        } else if (g.twod) {
+            strip_adjoint(A, false, i, j, j + 3, c, 0u, V, out, true, pay, pQ);
+            if (j < 3 || j >= g.ny - 3) {
+                for (int gq = 0; gq < 6; ++gq) {
+                    const int gj = (gq < 3) ? -1 - gq : g.ny + gq - 3;
+                    unsigned fl;
+                    const long long s = usrc(g, i, gj, fl);
+                    const bool owner = (s == c) || (s < 0 && j == ((gq < 3) ? 0 : g.ny - 1));
+                    if (owner) strip_adjoint(A, false, i, gj, gj + 3, s, fl, V, out, s == c, pay, pQ);
+                }
             }
         }
-        if (g.twod && (j < 3 || j >= g.ny - 3)) {
-            for (int gq = 0; gq < 6; ++gq) {
-                const int gj = (gq < 3) ? -1 - gq : g.ny + gq - 3;
-                unsigned fl;
-                const long long s = usrc(g, i, gj, fl);
-                const bool owner = (s == c) || (s < 0 && j == ((gq < 3) ? 0 : g.ny - 1));
-                if (owner) strip_adjoint(A, false, i, gj, gj + 3, s, fl, V, out, s == c, pay, pQ);
-            }
-        }
+    }
+    if (ydir) {
+#pragma unroll
+        for (int f = 0; f < NU5; ++f) ysum[f][lc] = out[f];
+    }
+    __syncthreads();
+    if (!ydir && c < A.n) {
+#pragma unroll
+        for (int f = 0; f < NU5; ++f) out[f] += ysum[f][lc];
         // explicit source S4 = -k r exp(-Ea/T), T = p/(rho R)
         const PGrad P = pgrad(g, V);
         const double mu4 = A.b * A.dt * A.lamW[(size_t)4 * A.n + c];
@@ -483,57 +492,127 @@ __global__ __launch_bounds__(AWG) void adj_cell(AdjArgs A) {
         A.part[(size_t)blockIdx.x * 4 + 2] = s2;
         A.part[(size_t)blockIdx.x * 4 + 3] = s3;
     }
-    if (!last_block(A.cnt, gridDim.x, &flag)) return;
-    if (threadIdx.x != 0) return;
-    double sax = 0.0, say = 0.0, sQ = 0.0, sEa = 0.0;
-    for (int q = 0; q < A.nbd; ++q) {
-        sax += A.part[(size_t)q * 4 + 0];
-        say += A.part[(size_t)q * 4 + 1];
-        sQ += A.part[(size_t)q * 4 + 2];
-        sEa += A.part[(size_t)q * 4 + 3];
-    }
-    for (int d = 0; d < (g.twod ? 2 : 1); ++d) {
-        const double mua = d == 0 ? sax : say;
-        const long long ca = A.argm[d];
-        if (ca < 0 || ca >= A.n) continue;   // no cell attained the maximum (cannot happen for finite data)
-        double V[NU5];
+}
+
+// D: one workgroup; the block partials summed in a fixed order, then the alpha
+// adjoints at the argmax cells and, if asked, the loss seed of a state at the
+// probes. Targets that share a cell are summed in target order and applied by
+// one thread, so the result does not depend on thread timing.
+constexpr int MAXT = 2 + MAXP;
+
+__global__ __launch_bounds__(AWG) void adj_finish(AdjArgs A) {
+    __shared__ double sh[8];
+    __shared__ double red[4];
+    __shared__ double dlam[MAXT][NU5], dacc[MAXT][NU5], dth[MAXT];
+    __shared__ long long tc[MAXT];
+    __shared__ int uselam[MAXT];
+    const AdjGrid& g = A.g;
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = threadIdx.x; q < A.nbd; q += AWG) {
 #pragma unroll
-        for (int f = 0; f < NU5; ++f) V[f] = A.V[(size_t)f * A.n + ca];
-        const PGrad P = pgrad(g, V);
-        const double rho = V[0];
-        const double cs = sqrt(g.gamma * P.p / rho);
-        const double w = d == 0 ? P.u : P.v;
-        const double sg = (w > 0.0) ? 1.0 : ((w < 0.0) ? -1.0 : 0.0);
-        const double kc = g.gamma / (2.0 * cs * rho);
-        double gr[NU5];
-        gr[0] = kc * (P.pr - P.p / rho) - sg * w / rho;
-        gr[1] = kc * P.pm + (d == 0 ? sg / rho : 0.0);
-        gr[2] = kc * P.pn + (d == 1 ? sg / rho : 0.0);
-        gr[3] = kc * P.pE;
-        gr[4] = kc * P.pY;
+        for (int k = 0; k < 4; ++k) s4[k] += A.part[(size_t)q * 4 + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double t = block_sum(s4[k], sh);
+        if (threadIdx.x == 0) red[k] = t;
+    }
+    __syncthreads();
+    const int nal = g.twod ? 2 : 1;
+    const int nsd = A.seedU ? A.np : 0;
+    const int T = nal + nsd;
+    const int k = threadIdx.x;
+    if (k < T) {
+        long long cell = -1;
+        double dl[NU5], da[NU5], th = 0.0;
+        int ul = 0;
+#pragma unroll
+        for (int f = 0; f < NU5; ++f) dl[f] = da[f] = 0.0;
+        if (k < nal) {
+            const int d = k;
+            const double mua = red[d];
+            const long long ca = A.argm[d];
+            if (ca >= 0 && ca < A.n) {   // (no cell attains the maximum only for non-finite data)
+                cell = ca;
+                double Vc[NU5];
+#pragma unroll
+                for (int f = 0; f < NU5; ++f) Vc[f] = A.V[(size_t)f * A.n + ca];
+                const PGrad P = pgrad(g, Vc);
+                const double rho = Vc[0];
+                const double cs = sqrt(g.gamma * P.p / rho);
+                const double w = d == 0 ? P.u : P.v;
+                const double sg = (w > 0.0) ? 1.0 : ((w < 0.0) ? -1.0 : 0.0);
+                const double kc = g.gamma / (2.0 * cs * rho);
+                double gr[NU5];
+                gr[0] = kc * (P.pr - P.p / rho) - sg * w / rho;
+                gr[1] = kc * P.pm + (d == 0 ? sg / rho : 0.0);
+                gr[2] = kc * P.pn + (d == 1 ? sg / rho : 0.0);
+                gr[3] = kc * P.pE;
+                gr[4] = kc * P.pY;
+#pragma unroll
+                for (int f = 0; f < NU5; ++f) {
+                    dl[f] = mua * gr[f];
+                    da[f] = A.add_out ? mua * gr[f] : 0.0;
+                }
+                ul = 1;
+                th = mua * kc * P.pQ;
+            }
+        } else {
+            // loss seed of the step start state: acc += dt w_q dp/dU at probe q
+            const int q = k - nal;
+            cell = A.pc[q];
+            double Vc[NU5];
+#pragma unroll
+            for (int f = 0; f < NU5; ++f) Vc[f] = A.seedU[(size_t)f * A.n + cell];
+            const PGrad P = pgrad(g, Vc);
+            const double s = A.dt * A.pw[q];
+            da[0] = s * P.pr;
+            da[1] = s * P.pm;
+            da[2] = s * P.pn;
+            da[3] = s * P.pE;
+            da[4] = s * P.pY;
+            th = s * P.pQ;
+        }
+        tc[k] = cell;
+        uselam[k] = ul;
+        dth[k] = th;
 #pragma unroll
         for (int f = 0; f < NU5; ++f) {
-            A.lamOut[(size_t)f * A.n + ca] += mua * gr[f];
-            if (A.add_out) A.acc[(size_t)f * A.n + ca] += mua * gr[f];
+            dlam[k][f] = dl[f];
+            dacc[k][f] = da[f];
         }
-        sQ += mua * kc * P.pQ;
     }
-    A.theta[0] += sQ;
-    A.theta[1] += sEa;
-    if (A.seedU) {
-        // loss seed of the step start state: acc += dt sum_q w_q dp/dU at the probes
-        for (int q = 0; q < A.np; ++q) {
-            double V[NU5];
-            for (int f = 0; f < NU5; ++f) V[f] = A.seedU[(size_t)f * A.n + A.pc[q]];
-            const PGrad P = pgrad(g, V);
-            const double s = A.dt * A.pw[q];
-            A.acc[(size_t)0 * A.n + A.pc[q]] += s * P.pr;
-            A.acc[(size_t)1 * A.n + A.pc[q]] += s * P.pm;
-            A.acc[(size_t)2 * A.n + A.pc[q]] += s * P.pn;
-            A.acc[(size_t)3 * A.n + A.pc[q]] += s * P.pE;
-            A.acc[(size_t)4 * A.n + A.pc[q]] += s * P.pY;
-            A.theta[0] += s * P.pQ;
+    __syncthreads();
+    if (k < T && tc[k] >= 0) {
+        bool first = true;
+        for (int q = 0; q < k; ++q) first = first && (tc[q] != tc[k]);
+        if (first) {
+            double sl[NU5], sa[NU5];
+            int ul = 0;
+#pragma unroll
+            for (int f = 0; f < NU5; ++f) sl[f] = sa[f] = 0.0;
+            for (int q = k; q < T; ++q) {
+                if (tc[q] != tc[k]) continue;
+                ul |= uselam[q];
+#pragma unroll
+                for (int f = 0; f < NU5; ++f) {
+                    sl[f] += dlam[q][f];
+                    sa[f] += dacc[q][f];
+                }
+            }
+            const long long cc = tc[k];
+#pragma unroll
+            for (int f = 0; f < NU5; ++f) {
+                if (ul) A.lamOut[(size_t)f * A.n + cc] += sl[f];
+                A.acc[(size_t)f * A.n + cc] += sa[f];
+            }
         }
+    }
+    if (threadIdx.x == 0) {
+        double sQ = red[2];
+        for (int q = 0; q < T; ++q) sQ += dth[q];
+        A.theta[0] += sQ;
+        A.theta[1] += red[3];
     }
 }
 
@@ -601,6 +680,7 @@ __global__ void adj_chain_sum(const double* part, int nb, double* theta) {
 hipError_t adj_alpha_launch(const AlphaArgs& P, hipStream_t s) {
     if (P.nsteps <= 0) return hipSuccess;
     adj_alpha<<<dim3(P.nbd, 3 * P.nsteps), AWG, 0, s>>>(P);
+    adj_alpha_reduce<<<3 * P.nsteps, AWG, 0, s>>>(P);
     return hipGetLastError();
 }
 
@@ -608,6 +688,7 @@ hipError_t adj_stage(const AdjArgs& A, hipStream_t s) {
     const int ni = (A.g.nx + 1) * A.g.ny + (A.g.twod ? A.g.nx * (A.g.ny + 1) : 0);
     adj_iface<<<(ni + AWG - 1) / AWG, AWG, 0, s>>>(A);
     adj_cell<<<A.nbd, AWG, 0, s>>>(A);
+    adj_finish<<<1, AWG, 0, s>>>(A);
     return hipGetLastError();
 }
 

@@ -15,6 +15,9 @@
 
 using namespace janc;
 
+static_assert(MAXP == JANC_MAX_PROBES, "probe limit of the adjoint kernels");
+static_assert(MAXF == JANC_MAX_FIELDS && MAXL == JANC_MAX_LEVELS, "table limits");
+
 struct janc_plan;
 
 struct janc_ctx {
@@ -31,10 +34,10 @@ struct janc_ctx {
     janc_grid ugrid{};
     janc_physics uphys{};
     // adjoint workspace (grown on demand)
-    std::vector<void*> adj_bufs;
-    size_t adj_key = 0;
     double* adj_mem = nullptr;
     size_t adj_doubles = 0;
+    hipStream_t adj_stream = nullptr;   // auxiliary stream of the adjoint's recompute
+    hipEvent_t adj_ev[5] = {};
 };
 
 struct GraphKey {
@@ -595,6 +598,7 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
         return fail(c, JANC_EINVAL, "adjoint grid needs nx >= 3 and ny = 1 or ny >= 3");
     const long long n = (long long)g->nx * g->ny;
     if (n > (1ll << 31) - 1) return fail(c, JANC_EINVAL, "grid too large for the adjoint");
+    if (np < 0 || np > JANC_MAX_PROBES) return fail(c, JANC_EINVAL, "between 0 and %d probes", JANC_MAX_PROBES);
     for (int q = 0; q < np; ++q)
         if (pc[q] < 0 || pc[q] >= n) return fail(c, JANC_EINVAL, "probe cell %d out of range", q);
     janc_status st = uniform_plan(c, g, ph);
@@ -618,7 +622,8 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     ag.Ea = ph->Ea;
     ag.k = ph->k;
     ag.dirU = P->ddir;
-    const int nbd = (int)((n + 255) / 256);          // cell blocks of the adjoint kernels
+    const int nba = (int)((n + 255) / 256);          // cell blocks of the alpha kernel
+    const int nbd = (int)((n + 127) / 128);          // blocks of the cell kernel (128 cells each)
     const long long nix = (long long)(g->nx + 1) * g->ny;
     const long long niy = ag.twod ? (long long)g->nx * (g->ny + 1) : 0;
     const long long n5 = 5 * n;
@@ -627,12 +632,22 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     struct Seg { size_t off, len; };
     size_t tot = 0;
     auto take = [&](size_t len) { Seg r{tot, len}; tot += (len + 31) & ~(size_t)31; return r; };
-    const Seg sCk = take((size_t)nseg * n5), sS0 = take((size_t)(K + 1) * n5), sS1 = take((size_t)K * n5),
-              sS2 = take((size_t)K * n5), sLam = take(n5), sLA = take(n5), sLB = take(n5), sAcc = take(n5),
+    // segment storage (stage inputs, alpha and argmax) twice: the recompute of
+    // segment sg - 1 on the auxiliary stream overlaps the reverse sweep of sg
+    Seg sS0[2], sS1[2], sS2[2], sApart[2], sAlpha[2], sArgm[2];
+    const Seg sCk = take((size_t)nseg * n5);
+    for (int b = 0; b < 2; ++b) {
+        sS0[b] = take((size_t)(K + 1) * n5);
+        sS1[b] = take((size_t)K * n5);
+        sS2[b] = take((size_t)K * n5);
+        sApart[b] = take((size_t)nsl * nba * 4);
+        sAlpha[b] = take(2 * (size_t)nsl);
+        sArgm[b] = take((size_t)nsl);
+    }
+    const Seg sLam = take(n5), sLA = take(n5), sLB = take(n5), sAcc = take(n5),
               sT0 = take(n), sT1 = take(n), sCx = take(50 * nix), sCy = take(50 * niy),
-              sPart = take(4 * (size_t)nbd + 8), sApart = take((size_t)nsl * nbd * 4),
-              sAlpha = take(2 * (size_t)nsl), sArgm = take((size_t)nsl), sCnt = take((size_t)nsl / 2 + 2),
-              sMisc = take(16), sPc = take(np + 1), sPw = take(np + 1);
+              sPart = take(4 * (size_t)nbd + 8), sMisc = take(16), sPc = take(np + 1),
+              sPw = take(np + 1);
     if (tot > c->adj_doubles) {
         if (c->adj_mem) hipFree(c->adj_mem);
         c->adj_mem = nullptr;
@@ -643,9 +658,18 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     double* M = c->adj_mem;
     auto at = [&](const Seg& q) { return M + q.off; };
     double* ck = at(sCk);
-    double* S0 = at(sS0);
-    double* S1 = at(sS1);
-    double* S2 = at(sS2);
+    double* S0b[2] = {at(sS0[0]), at(sS0[1])};
+    double* S1b[2] = {at(sS1[0]), at(sS1[1])};
+    double* S2b[2] = {at(sS2[0]), at(sS2[1])};
+    double* S0 = S0b[0];
+    double* S1 = S1b[0];
+    double* S2 = S2b[0];
+    if (!c->adj_stream) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->adj_stream, hipStreamNonBlocking), "stream");
+        for (int q = 0; q < 5; ++q)
+            HIPCHK(c, hipEventCreateWithFlags(&c->adj_ev[q], hipEventDisableTiming), "event");
+    }
+    hipStream_t s2 = c->adj_stream;
     double* lam = at(sLam);
     double* lA = at(sLA);
     double* lB = at(sLB);
@@ -662,24 +686,22 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     HIPCHK(c, hipMemsetAsync(loss, 0, sizeof(double), s), "memset");
     HIPCHK(c, hipMemsetAsync(theta, 0, 2 * sizeof(double), s), "memset");
     HIPCHK(c, hipMemsetAsync(lam, 0, sizeof(double) * n5, s), "memset");
-    unsigned* cnt = (unsigned*)at(sCnt);               // [nsl] alpha slices, [nsl] the cell kernel
-    HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(unsigned) * (nsl + 1), s), "memset");
     // U0 from the primitives (the Q dependence of E0 is chained at the end)
     HIPCHK(c, launch_prim_to_cons(ONESTEP, 0, nullptr, ph->gamma, ph->R, ph->Q, n, W0, ck, T0, n, n, s),
            "init_state");
     double* tdev = misc;   // forward time (unused by fixed dt), misc[1..] scratch
     const StageArgs base = base_args(P, tm, ck, T0, tdev, nullptr, 0);
-    auto entry = [&](double* U) -> hipError_t {
-        hipError_t e = launch_clear_reduce(base.red, -1, s);
-        if (e == hipSuccess) e = launch_zero_int(P->dstep, s);
+    auto entry = [&](double* U, hipStream_t q) -> hipError_t {
+        hipError_t e = launch_clear_reduce(base.red, -1, q);
+        if (e == hipSuccess) e = launch_zero_int(P->dstep, q);
         StageArgs a0 = base;
         a0.Uin = U;
         a0.Tin = T0;
         a0.Tout = T0;
-        if (e == hipSuccess) e = launch_init(ONESTEP, 0, P->tile_w, a0, s);
+        if (e == hipSuccess) e = launch_init(ONESTEP, 0, P->tile_w, a0, q);
         return e;
     };
-    auto stage = [&](int stn, double* Un, double* Uin, double* Uout) -> hipError_t {
+    auto stage = [&](int stn, double* Un, double* Uin, double* Uout, hipStream_t q) -> hipError_t {
         StageArgs a = base;
         a.stage = stn;
         a.U0 = Un;
@@ -690,19 +712,19 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
         if (stn == 3) { a.Tin = T0; a.Tout = T1; }
         if (stn == 1) { a.Tin = T1; a.Tout = T0; }
         a.reduce_out = 1;
-        return launch_stage(ONESTEP, 0, P->kind_mask, P->tile_w, a, 0, a.ntiles, s);
+        return launch_stage(ONESTEP, 0, P->kind_mask, P->tile_w, a, 0, a.ntiles, q);
     };
     const double dt = tm->dt_fixed;
     // ---- forward pass with checkpoints and the probe loss
-    HIPCHK(c, entry(ck), "adjoint forward entry");
+    HIPCHK(c, entry(ck, s), "adjoint forward entry");
     HIPCHK(c, hipMemcpyAsync(T1, T0, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy");
     double* cur = ck;
     for (int step = 0; step < N; ++step) {
         double* nxt = (step + 1 < N && (step + 1) % K == 0) ? ck + (size_t)((step + 1) / K) * n5
                                                            : ((cur == S0) ? S0 + n5 : S0);
-        HIPCHK(c, stage(1, cur, cur, S1), "forward stage");
-        HIPCHK(c, stage(2, cur, S1, S2), "forward stage");
-        HIPCHK(c, stage(3, cur, S2, nxt), "forward stage");
+        HIPCHK(c, stage(1, cur, cur, S1, s), "forward stage");
+        HIPCHK(c, stage(2, cur, S1, S2, s), "forward stage");
+        HIPCHK(c, stage(3, cur, S2, nxt, s), "forward stage");
         HIPCHK(c, adj_loss_launch(ag, nxt, n, dpc, dpw, np, dt, loss, s), "loss");
         cur = nxt;
     }
@@ -714,66 +736,82 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     A.cx = at(sCx);
     A.cy = at(sCy);
     A.part = at(sPart);
-    A.cnt = cnt + nsl;
     A.nbd = nbd;
     A.theta = theta;
     A.pc = dpc;
     A.pw = dpw;
     A.np = np;
-    double* alpha = at(sAlpha);
-    int* argm = (int*)at(sArgm);
     AlphaArgs AP{};
     AP.g = ag;
     AP.n = n;
-    AP.base[0] = S0;
-    AP.base[1] = S1;
-    AP.base[2] = S2;
     AP.step_stride = n5;
-    AP.nbd = nbd;
-    AP.part = at(sApart);
-    AP.cnt = cnt;
-    AP.alpha = alpha;
-    AP.argm = argm;
+    AP.nbd = nba;
     HIPCHK(c, adj_seed_launch(ag, cur, n, dpc, dpw, np, dt, lam, theta, s), "seed");
+    hipEvent_t evFwd = c->adj_ev[0], evRec[2] = {c->adj_ev[1], c->adj_ev[2]},
+               evRev[2] = {c->adj_ev[3], c->adj_ev[4]};
+    bool used[2] = {false, false};
+    // recompute segment sg into buffer b (auxiliary stream), storing the three
+    // stage inputs of every step, then alpha and its argmax of all of them
+    auto recompute = [&](int sg, int b) -> hipError_t {
+        const int n0 = sg * K, m1 = std::min(N, n0 + K) - n0;
+        double *R0 = S0b[b], *R1 = S1b[b], *R2 = S2b[b];
+        hipError_t e = hipSuccess;
+        if (used[b]) e = hipStreamWaitEvent(s2, evRev[b], 0);   // its last reverse sweep is done
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(R0, ck + (size_t)sg * n5, sizeof(double) * n5, hipMemcpyDeviceToDevice, s2);
+        if (e == hipSuccess) e = entry(R0, s2);
+        for (int m = 0; m < m1 && e == hipSuccess; ++m) {
+            double* u0 = R0 + (size_t)m * n5;
+            e = stage(1, u0, u0, R1 + (size_t)m * n5, s2);
+            if (e == hipSuccess) e = stage(2, u0, R1 + (size_t)m * n5, R2 + (size_t)m * n5, s2);
+            // the last step of the segment needs only its first two stage outputs
+            if (e == hipSuccess && m + 1 < m1)
+                e = stage(3, u0, R2 + (size_t)m * n5, R0 + (size_t)(m + 1) * n5, s2);
+        }
+        AlphaArgs ap = AP;
+        ap.base[0] = R0;
+        ap.base[1] = R1;
+        ap.base[2] = R2;
+        ap.nsteps = m1;
+        ap.part = at(sApart[b]);
+        ap.alpha = at(sAlpha[b]);
+        ap.argm = (int*)at(sArgm[b]);
+        if (e == hipSuccess) e = adj_alpha_launch(ap, s2);
+        if (e == hipSuccess) e = hipEventRecord(evRec[b], s2);
+        return e;
+    };
+    HIPCHK(c, hipEventRecord(evFwd, s), "event");
+    HIPCHK(c, hipStreamWaitEvent(s2, evFwd, 0), "event");
+    HIPCHK(c, recompute(nseg - 1, (nseg - 1) & 1), "recompute");
     for (int sg = nseg - 1; sg >= 0; --sg) {
-        const int n0 = sg * K, n1 = std::min(N, n0 + K), m1 = n1 - n0;
-        // recompute the segment, storing the three stage inputs of every step
-        HIPCHK(c, hipMemcpyAsync(S0, ck + (size_t)sg * n5, sizeof(double) * n5, hipMemcpyDeviceToDevice, s), "copy");
-        HIPCHK(c, entry(S0), "recompute entry");
-        for (int m = 0; m < m1 - 1; ++m) {
-            double* u0 = S0 + (size_t)m * n5;
-            HIPCHK(c, stage(1, u0, u0, S1 + (size_t)m * n5), "recompute stage");
-            HIPCHK(c, stage(2, u0, S1 + (size_t)m * n5, S2 + (size_t)m * n5), "recompute stage");
-            HIPCHK(c, stage(3, u0, S2 + (size_t)m * n5, S0 + (size_t)(m + 1) * n5), "recompute stage");
-        }
-        {   // the last step of the segment needs only its first two stage outputs
-            const int m = m1 - 1;
-            double* u0 = S0 + (size_t)m * n5;
-            HIPCHK(c, stage(1, u0, u0, S1 + (size_t)m * n5), "recompute stage");
-            HIPCHK(c, stage(2, u0, S1 + (size_t)m * n5, S2 + (size_t)m * n5), "recompute stage");
-        }
-        // alpha and its argmax of all 3 m1 stage inputs
-        AP.nsteps = m1;
-        HIPCHK(c, adj_alpha_launch(AP, s), "adjoint alpha");
+        const int b = sg & 1;
+        const int n0 = sg * K, m1 = std::min(N, n0 + K) - n0;
+        if (sg >= 1) HIPCHK(c, recompute(sg - 1, 1 - b), "recompute");
+        HIPCHK(c, hipStreamWaitEvent(s, evRec[b], 0), "event");
+        double *R0 = S0b[b], *R1 = S1b[b], *R2 = S2b[b];
+        const double* alpha = at(sAlpha[b]);
+        const int* argm = (const int*)at(sArgm[b]);
         for (int m = m1 - 1; m >= 0; --m) {
             AdjArgs a3 = A;   // stage 3: W = U/3 + 2/3 (V + dt L(V)), V = U^(2)
-            a3.V = S2 + (size_t)m * n5; a3.lamW = lam; a3.lamOut = lA; a3.acc = acc;
+            a3.V = R2 + (size_t)m * n5; a3.lamW = lam; a3.lamOut = lA; a3.acc = acc;
             a3.b = 2.0 / 3.0; a3.a = 1.0 / 3.0; a3.init_acc = 1; a3.add_out = 0;
             a3.alpha = alpha + 2 * (3 * m + 2); a3.argm = argm + 2 * (3 * m + 2);
             HIPCHK(c, adj_stage(a3, s), "adjoint stage 3");
             AdjArgs a2 = A;   // stage 2: W = 3/4 U + 1/4 (V + dt L(V)), V = U^(1)
-            a2.V = S1 + (size_t)m * n5; a2.lamW = lA; a2.lamOut = lB; a2.acc = acc;
+            a2.V = R1 + (size_t)m * n5; a2.lamW = lA; a2.lamOut = lB; a2.acc = acc;
             a2.b = 0.25; a2.a = 0.75; a2.init_acc = 0; a2.add_out = 0;
             a2.alpha = alpha + 2 * (3 * m + 1); a2.argm = argm + 2 * (3 * m + 1);
             HIPCHK(c, adj_stage(a2, s), "adjoint stage 2");
             AdjArgs a1 = A;   // stage 1: W = V + dt L(V), V = U^n; then the loss seed of U^n
-            a1.V = S0 + (size_t)m * n5; a1.lamW = lB; a1.lamOut = lA; a1.acc = acc;
+            a1.V = R0 + (size_t)m * n5; a1.lamW = lB; a1.lamOut = lA; a1.acc = acc;
             a1.b = 1.0; a1.a = 0.0; a1.init_acc = 0; a1.add_out = 1;
             a1.alpha = alpha + 2 * (3 * m); a1.argm = argm + 2 * (3 * m);
-            a1.seedU = (n0 + m >= 1) ? S0 + (size_t)m * n5 : nullptr;
+            a1.seedU = (n0 + m >= 1) ? R0 + (size_t)m * n5 : nullptr;
             HIPCHK(c, adj_stage(a1, s), "adjoint stage 1");
             std::swap(lam, acc);
         }
+        HIPCHK(c, hipEventRecord(evRev[b], s), "event");
+        used[b] = true;
     }
     // chain dL/dU0 to the primitives; E0 = p/(gamma-1) + rho |u|^2/2 + rho Y Q adds to dL/dQ
     HIPCHK(c, adj_chain_launch(ag, W0, lam, n, gW, A.part, theta, s), "chain");
@@ -813,6 +851,10 @@ void janc_destroy(janc_ctx* c) {
     plan_free(c->uplan);
     if (c->dmech) hipFree(c->dmech);
     if (c->dstatus) hipFree(c->dstatus);
+    if (c->adj_mem) hipFree(c->adj_mem);
+    for (hipEvent_t e : c->adj_ev)
+        if (e) hipEventDestroy(e);
+    if (c->adj_stream) hipStreamDestroy(c->adj_stream);
     delete c;
 }
 

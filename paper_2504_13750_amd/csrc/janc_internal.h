@@ -11,6 +11,7 @@ constexpr int MAXF = 16;        // conserved fields (4 + species - 1)
 constexpr int MAXL = 8;         // refinement levels per domain
 constexpr int MAXS = 12;        // species
 constexpr int MAXR = 64;        // reactions
+constexpr int MAXP = 8;         // adjoint probes (JANC_MAX_PROBES)
 constexpr int MAXLIST = 3;      // reactant / product molecules per reaction
 constexpr double RU = 8.314472;     // J/(mol K), paper Sec. 4.1
 constexpr double PATM = 101325.0;   // Pa, Eq. 4.9
@@ -149,7 +150,6 @@ struct AdjArgs {
     const double* alpha;      // [2] alpha_x, alpha_y of the stage input
     const int* argm;          // [2] lowest cell attaining them
     double* part;             // [nbd][4] block partials
-    unsigned* cnt;            // completion counter of the stage's cell kernel
     int nbd;                  // cell blocks
     double* theta;            // [2]: dL/dQ, dL/dEa
     const double* seedU;      // state whose probe loss seeds acc after this stage (or null)
@@ -168,7 +168,6 @@ struct AlphaArgs {
     int nsteps;
     int nbd;
     double* part;             // [slices][nbd][4]
-    unsigned* cnt;            // [slices]
     double* alpha;            // [slices][2]
     int* argm;                // [slices][2]
 };

@@ -104,6 +104,45 @@ def test_full_gradient_brute_force_tiny_grid(nsteps):
     assert err <= 1e-10
 
 
+def test_coinciding_probes_match_oracle():
+    """Probes that share a cell are applied together, in probe order: gradients along a
+    random direction in all fields and dL/dQ still equal the oracle's tangents. (Weights
+    of one sign: a dL/dQ that cancels to a small fraction of its terms has no relative
+    accuracy to test.)"""
+    c, probes, w = _untied()
+    probes = np.array([probes[0], probes[0], probes[1], probes[0], probes[2]], np.int32)
+    w = np.array([1.0, 0.25, 0.5, 2.0, 1.5])
+    L, gW, gth = _gpu_adjoint(c, 8, probes, w, ckpt=3)
+    Lo, dQ = oracle.loss_tangent(c, c.W, 8, probes, w, c.dt_fixed, dQ=1.0)
+    v = np.random.default_rng(77).normal(size=c.W.shape)
+    _, dv = oracle.loss_tangent(c, c.W, 8, probes, w, c.dt_fixed, dW0=v)
+    got = float(np.sum(gW * v))
+    print(f"  loss {L:.15e} / {Lo:.15e}; dQ {gth[0]:.12e} / {dQ:.12e}; <g, v> {got:.12e} / "
+          f"{dv:.12e}", flush=True)
+    assert L == pytest.approx(Lo, rel=1e-12)
+    assert gth[0] == pytest.approx(dQ, rel=1e-10, abs=0.0)
+    assert got == pytest.approx(dv, rel=1e-10, abs=0.0)
+
+
+@pytest.mark.parametrize("bad", ["count", "cell"])
+def test_bad_probes_rejected(bad):
+    c, probes, w = _small()
+    if bad == "count":
+        probes = np.resize(probes, 9).astype(np.int32)
+        w = np.ones(9)
+    else:
+        probes = probes.copy()
+        probes[1] = c.nx * c.ny
+    torch, dev = torch_dev()
+    ctx = janc.Context(janc.ONESTEP)
+    W0 = torch.tensor(c.W, dtype=torch.float64, device=dev)
+    with pytest.raises(janc.JancError) as ei:
+        ctx.adjoint(janc.grid_of(c), janc.physics_of(c), janc.make_time(0.0, c.dt_fixed, 0.0),
+                    W0, 4, 2, probes, w)
+    assert ei.value.code == -1
+    ctx.close()
+
+
 def test_checkpoint_interval_does_not_change_result():
     c, probes, w = _small()
     a = _gpu_adjoint(c, 12, probes, w, ckpt=12)
