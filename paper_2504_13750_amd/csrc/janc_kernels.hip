@@ -37,7 +37,7 @@ struct Geom {
     static constexpr int NYS = TWO ? TX * (TY + 6) : 0; // y split fluxes, 3 halo rows
     static constexpr int NIX = (TX + 1) * TY;           // x interfaces
     static constexpr int NIY = TWO ? TX * (TY + 1) : 0; // y interfaces
-    static constexpr int NTASK = 2 * (NIX + NIY);       // one WENO5 reconstruction each
+    static constexpr int NEXT = 2 * TY + (TWO ? 2 * TX : 0);  // right column / top row, both sides
     // LDS doubles: F+/F- and G+/G-, the four one-sided interface values, scratch
     static constexpr int LDS = 2 * NXS + 2 * NYS + 2 * NIX + 2 * NIY + 16;
 
@@ -139,6 +139,34 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
     }
     double unew[NU];
 
+    // reconstruction tasks of this thread (see phase 1)
+    const bool vxi = (olj < th) && (oli <= tw);
+    const bool vyi = G::TWO && (oli < tw) && (olj <= th);
+    const int bxi = olj * G::PW + oli, byi = olj * TX + oli;
+    const int rxi = olj * (TX + 1) + oli, ryi = olj * TX + oli;
+    bool ext_ok = false;
+    int ext_str = 1;
+    const double* ext_base = fpx;
+    double* ext_out = hxp;
+    if (tid < G::NEXT) {
+        const int e = tid;
+        if (e < 2 * TY) {          // x interface TX of row e % TY, F+ then F-
+            const int side = e / TY, row = e - side * TY;
+            ext_ok = row < th && tw == TX;
+            const int r = row * (TX + 1) + TX, o = row * G::PW + TX;
+            ext_base = side ? fmx + o + 5 : fpx + o;
+            ext_str = side ? -1 : 1;
+            ext_out = (side ? hxm : hxp) + r;
+        } else {                   // y interface TY of column, F+ then F-
+            const int h = e - 2 * TY, side = h / TX, col = h - side * TX;
+            ext_ok = col < tw && th == TY;
+            const int r = TY * TX + col, o = TY * TX + col;
+            ext_base = side ? fmy + o + 5 * TX : fpy + o;
+            ext_str = side ? -TX : TX;
+            ext_out = (side ? hym : hyp) + r;
+        }
+    }
+
     // ---------------- phase 1: per component split fluxes, WENO5, RK update
 #pragma unroll
     for (int f = 0; f < NU; ++f) {
@@ -166,40 +194,27 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
             }
         }
         __syncthreads();
-        // one-sided WENO5 reconstructions, spread evenly over the workgroup:
-        // task = (direction, side, interface); the F- side reads its stencil mirrored
-        for (int t = tid; t < G::NTASK; t += WG) {
-            int r = t;
-            const bool isy = G::TWO && r >= 2 * G::NIX;
-            if (isy) r -= 2 * G::NIX;
-            const int n = isy ? G::NIY : G::NIX;
-            const bool minus = r >= n;
-            if (minus) r -= n;
-            int row, col, stride, boff;
-            bool valid;
-            if (!isy) {
-                row = r / (TX + 1);
-                col = r - row * (TX + 1);
-                valid = row < th && col <= tw;
-                boff = row * G::PW + col;
-                stride = 1;
-            } else {
-                row = r / TX;
-                col = r - row * TX;
-                valid = col < tw && row <= th;
-                boff = row * TX + col;
-                stride = TX;
+        // one-sided WENO5 reconstructions: each thread takes the left x interface
+        // and the lower y interface of its own position (both sides, fixed LDS
+        // offsets); the right column and top row of interfaces are the extra tasks
+        // of the first threads. F- reads its stencil mirrored.
+        if (vxi) {
+            const double* P = fpx + bxi;
+            const double* Mn = fmx + bxi;
+            hxp[rxi] = weno5(P[0], P[1], P[2], P[3], P[4]);
+            hxm[rxi] = weno5(Mn[5], Mn[4], Mn[3], Mn[2], Mn[1]);
+        }
+        if constexpr (G::TWO) {
+            if (vyi) {
+                const double* P = fpy + byi;
+                const double* Mn = fmy + byi;
+                hyp[ryi] = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX]);
+                hym[ryi] = weno5(Mn[5 * TX], Mn[4 * TX], Mn[3 * TX], Mn[2 * TX], Mn[TX]);
             }
-            const double* base = isy ? (minus ? fmy : fpy) : (minus ? fmx : fpx);
-            base += boff;
-            if (minus) {
-                base += 5 * stride;
-                stride = -stride;
-            }
-            double* out = isy ? (minus ? hym : hyp) : (minus ? hxm : hxp);
-            if (valid)
-                out[r] = weno5(base[0], base[stride], base[2 * stride], base[3 * stride],
-                               base[4 * stride]);
+        }
+        if (ext_ok) {
+            const double* b = ext_base;
+            *ext_out = weno5(b[0], b[ext_str], b[2 * ext_str], b[3 * ext_str], b[4 * ext_str]);
         }
         __syncthreads();
         if (own) {
