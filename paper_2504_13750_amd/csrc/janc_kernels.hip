@@ -168,11 +168,17 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
     }
 
     // ---------------- phase 1: per component split fluxes, WENO5, RK update
+    // U^(0) of the owned cell (stages 2 and 3) is loaded PF components ahead of
+    // its use, so that its memory latency overlaps the reconstructions between.
+    constexpr int PF = 3;
+    const bool ld0 = own && stage != 1;
+    double u0q[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) u0q[k] = (ld0 && k < NU) ? a.U0[(size_t)k * a.pool + oc] : 0.0;
 #pragma unroll
     for (int f = 0; f < NU; ++f) {
-        // stage input U^(0) of the owned cell, issued ahead of the reconstruction
-        double u0 = 0.0;
-        if (own) u0 = (stage == 1) ? ur[0][f] : a.U0[(size_t)f * a.pool + oc];
+        const double u0 = (stage == 1) ? ur[0][f] : u0q[f % PF];
+        if (f + PF < NU) u0q[f % PF] = ld0 ? a.U0[(size_t)(f + PF) * a.pool + oc] : 0.0;
 #pragma unroll
         for (int q = 0; q < G::NPT; ++q) {
             const double uf = ur[q][f];
@@ -253,8 +259,11 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
                      scratch);
 }
 
+#ifndef STAGE_WAVES
+#define STAGE_WAVES 1
+#endif
 template <int M, int NU, int TX, int TY, bool HAS1D, bool HAS2D>
-__global__ __launch_bounds__(WG) void stage_kernel(StageArgs a, int first_tile, int owner_launch) {
+__global__ __launch_bounds__(WG, STAGE_WAVES) void stage_kernel(StageArgs a, int first_tile, int owner_launch) {
     constexpr int L2 = Geom<TX, TY>::LDS, L1 = Geom<WG, 1>::LDS;
     __shared__ double smem[(L2 > L1) ? L2 : L1];
     if (blockIdx.x == 0) stage_bookkeeping(a, owner_launch);
