@@ -55,11 +55,13 @@ __device__ long long usrc(const AdjGrid& g, int i, int j, unsigned& fl) {
     return (long long)j * g.nx + i;
 }
 
+// The cell loads are issued unconditionally (index clamped) so that the loads of
+// several points are in flight together; a Dirichlet row replaces them.
 __device__ __forceinline__ void load_src(const AdjArgs& A, long long s, unsigned fl, double (&u)[NU5]) {
-    if (s >= 0) {
+    const long long sc = s >= 0 ? s : 0;
 #pragma unroll
-        for (int f = 0; f < NU5; ++f) u[f] = A.V[(size_t)f * A.n + s];
-    } else {
+    for (int f = 0; f < NU5; ++f) u[f] = A.V[(size_t)f * A.n + sc];
+    if (s < 0) {
         const double* r = A.g.dirU + (size_t)(-s - 1) * (MAXF + 1);
 #pragma unroll
         for (int f = 0; f < NU5; ++f) u[f] = r[f];
@@ -232,15 +234,14 @@ __device__ __forceinline__ void split_flux(const double (&V)[NU5], double vn, do
     Fm = 0.5 * (F - al * V[f]);
 }
 
-// B: per interface, mu_Fhat = b dt (mu_right - mu_left)/dx and the reverse of
-// both WENO5 reconstructions; the six stencil states and their split fluxes
-// are formed here from the stage input.
-__global__ __launch_bounds__(AWG) void adj_iface(AdjArgs A) {
-    const int q = blockIdx.x * AWG + threadIdx.x;
+// B: per interface and component, mu_Fhat = b dt (mu_right - mu_left)/dx and
+// the reverse of both WENO5 reconstructions; the six stencil states and their
+// split fluxes are formed here from the stage input (component = blockIdx.y).
+template <int F>
+__device__ __forceinline__ void iface_component(const AdjArgs& A, int q) {
     const AdjGrid& g = A.g;
     const int nix = (g.nx + 1) * g.ny, niy = g.twod ? g.nx * (g.ny + 1) : 0;
     if (q >= nix + niy) return;
-    const double mscale = A.b * A.dt;
     const bool xdir = q < nix;
     int r, i0, j0, k, len, lidx;
     if (xdir) {
@@ -261,39 +262,45 @@ __global__ __launch_bounds__(AWG) void adj_iface(AdjArgs A) {
     const long long lstep = xdir ? 1 : g.nx;
     const double al = A.alpha[xdir ? 0 : 1];
     const double ih = xdir ? g.idx : g.idy;
+    const double lr = A.lamW[(size_t)F * A.n + ((k < len) ? lidx : 0)];
+    const double ll = A.lamW[(size_t)F * A.n + ((k > 0) ? lidx - lstep : 0)];
+    const double mr = (k < len) ? lr : 0.0;
+    const double ml = (k > 0) ? ll : 0.0;
+    const double fb = A.b * A.dt * (mr - ml) * ih;
     // stencil points t = 0..5 at positions k-3 .. k+2 along the sweep
-    double V[6][NU5], vn[6], pp[6];
     DevDomain D{};
     D.gamma = g.gamma;
     D.Q = g.Q;
+    double Fp[6], Fm[6];
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
         unsigned fl;
         const long long src = xdir ? usrc(g, i0 + t, j0, fl) : usrc(g, i0, j0 + t, fl);
-        load_src(A, src, fl, V[t]);
-        double vx, vy;
-        halo_prims<ONESTEP, NU5>(V[t], 0.0, D, nullptr, vx, vy, pp[t]);
-        vn[t] = xdir ? vx : vy;
+        double V[NU5], vx, vy, p;
+        load_src(A, src, fl, V);
+        halo_prims<ONESTEP, NU5>(V, 0.0, D, nullptr, vx, vy, p);
+        split_flux(V, xdir ? vx : vy, p, F, xdir, al, Fp[t], Fm[t]);
     }
-    double* outb = xdir ? A.cx : A.cy;
+    double gp[5], gm[5];
+    weno5_adj(Fp[0], Fp[1], Fp[2], Fp[3], Fp[4], fb, gp);
+    weno5_adj(Fm[5], Fm[4], Fm[3], Fm[2], Fm[1], fb, gm);
     const int ni = xdir ? nix : niy;
+    double* out = (xdir ? A.cx : A.cy) + (size_t)F * 10 * ni;
 #pragma unroll
-    for (int f = 0; f < NU5; ++f) {
-        const double mr = (k < len) ? A.lamW[(size_t)f * A.n + lidx] : 0.0;
-        const double ml = (k > 0) ? A.lamW[(size_t)f * A.n + lidx - lstep] : 0.0;
-        const double fb = mscale * (mr - ml) * ih;
-        double Fp[6], Fm[6];
-#pragma unroll
-        for (int t = 0; t < 6; ++t) split_flux(V[t], vn[t], pp[t], f, xdir, al, Fp[t], Fm[t]);
-        double gp[5], gm[5];
-        weno5_adj(Fp[0], Fp[1], Fp[2], Fp[3], Fp[4], fb, gp);
-        weno5_adj(Fm[5], Fm[4], Fm[3], Fm[2], Fm[1], fb, gm);
-        double* out = outb + (size_t)f * 10 * ni;
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {
-            out[(size_t)m * ni + r] = gp[m];
-            out[(size_t)(5 + m) * ni + r] = gm[4 - m];
-        }
+    for (int m = 0; m < 5; ++m) {
+        out[(size_t)m * ni + r] = gp[m];
+        out[(size_t)(5 + m) * ni + r] = gm[4 - m];
+    }
+}
+
+__global__ __launch_bounds__(AWG) void adj_iface(AdjArgs A) {
+    const int q = blockIdx.x * AWG + threadIdx.x;
+    switch (blockIdx.y) {
+        case 0: iface_component<0>(A, q); break;
+        case 1: iface_component<1>(A, q); break;
+        case 2: iface_component<2>(A, q); break;
+        case 3: iface_component<3>(A, q); break;
+        default: iface_component<4>(A, q); break;
     }
 }
 
@@ -311,11 +318,15 @@ __device__ __forceinline__ void gather_strip(const AdjArgs& A, bool xdir, int i,
         double ap = 0.0, am = 0.0;
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
+            // loads at clamped interfaces, then a select: all ten are in flight together
             const int Ip = xi - m, Im = xi - 1 - m;
-            const int rp = xdir ? j * (g.nx + 1) + Ip : Ip * g.nx + i;
-            const int rm = xdir ? j * (g.nx + 1) + Im : Im * g.nx + i;
-            if (Ip >= 0 && Ip <= len) ap += cf[(size_t)m * ni + rp];
-            if (Im >= 0 && Im <= len) am += cf[(size_t)(5 + m) * ni + rm];
+            const bool okp = Ip >= 0 && Ip <= len, okm = Im >= 0 && Im <= len;
+            const int Ipc = okp ? Ip : 0, Imc = okm ? Im : 0;
+            const int rp = xdir ? j * (g.nx + 1) + Ipc : Ipc * g.nx + i;
+            const int rm = xdir ? j * (g.nx + 1) + Imc : Imc * g.nx + i;
+            const double vp = cf[(size_t)m * ni + rp], vm = cf[(size_t)(5 + m) * ni + rm];
+            ap += okp ? vp : 0.0;
+            am += okm ? vm : 0.0;
         }
         mp[f] = ap;
         mm[f] = am;
@@ -616,10 +627,18 @@ __global__ __launch_bounds__(AWG) void adj_finish(AdjArgs A) {
     }
 }
 
-// Loss accumulation of the forward pass: loss += dt sum_q w_q p(U[cell_q]).
-__global__ void adj_loss(AdjGrid g, const double* U, long long n, const int* pc, const double* pw,
-                         int np, double dt, double* loss) {
-    if (threadIdx.x != 0) return;
+// Loss terms of a run of states: term[n0 + m - 1] = dt sum_q w_q p(U_m at cell_q)
+// for the states U_m = base + m * stride, m = 1 .. count - 1, then `last` (if not
+// null) as m = count. The terms are summed in step order at the end, so the loss
+// does not depend on how the run was cut into segments.
+__global__ __launch_bounds__(AWG) void adj_loss(AdjGrid g, const double* base, long long stride,
+                                                int count, const double* last, int n0, long long n,
+                                                const int* pc, const double* pw, int np, double dt,
+                                                double* term) {
+    const int ns = (count - 1) + (last ? 1 : 0);
+    const int si = blockIdx.x * AWG + threadIdx.x;
+    if (si >= ns) return;
+    const double* U = (si < count - 1) ? base + (size_t)(si + 1) * stride : last;
     double acc = 0.0;
     for (int q = 0; q < np; ++q) {
         double V[NU5];
@@ -627,7 +646,14 @@ __global__ void adj_loss(AdjGrid g, const double* U, long long n, const int* pc,
         const PGrad P = pgrad(g, V);
         acc += pw[q] * P.p;
     }
-    loss[0] += dt * acc;
+    term[n0 + si] = dt * acc;
+}
+
+__global__ void adj_loss_sum(const double* term, int nsteps, double* loss) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int q = 0; q < nsteps; ++q) s += term[q];
+    loss[0] = s;
 }
 
 // Loss seed of one state: lambda += dt sum_q w_q dp/dU at the probes, theta_Q += dt w_q dp/dQ.
@@ -686,15 +712,24 @@ hipError_t adj_alpha_launch(const AlphaArgs& P, hipStream_t s) {
 
 hipError_t adj_stage(const AdjArgs& A, hipStream_t s) {
     const int ni = (A.g.nx + 1) * A.g.ny + (A.g.twod ? A.g.nx * (A.g.ny + 1) : 0);
-    adj_iface<<<(ni + AWG - 1) / AWG, AWG, 0, s>>>(A);
+    adj_iface<<<dim3((ni + AWG - 1) / AWG, NU5), AWG, 0, s>>>(A);
     adj_cell<<<A.nbd, AWG, 0, s>>>(A);
     adj_finish<<<1, AWG, 0, s>>>(A);
     return hipGetLastError();
 }
 
-hipError_t adj_loss_launch(const AdjGrid& g, const double* U, long long n, const int* pc,
-                           const double* pw, int np, double dt, double* loss, hipStream_t s) {
-    adj_loss<<<1, 64, 0, s>>>(g, U, n, pc, pw, np, dt, loss);
+hipError_t adj_loss_launch(const AdjGrid& g, const double* base, long long stride, int count,
+                           const double* last, int n0, long long n, const int* pc, const double* pw,
+                           int np, double dt, double* term, hipStream_t s) {
+    const int ns = (count - 1) + (last ? 1 : 0);
+    if (ns <= 0) return hipSuccess;
+    adj_loss<<<(ns + AWG - 1) / AWG, AWG, 0, s>>>(g, base, stride, count, last, n0, n, pc, pw, np,
+                                                 dt, term);
+    return hipGetLastError();
+}
+
+hipError_t adj_loss_sum_launch(const double* term, int nsteps, double* loss, hipStream_t s) {
+    adj_loss_sum<<<1, 64, 0, s>>>(term, nsteps, loss);
     return hipGetLastError();
 }
 

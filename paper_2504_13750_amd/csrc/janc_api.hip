@@ -647,7 +647,7 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     const Seg sLam = take(n5), sLA = take(n5), sLB = take(n5), sAcc = take(n5),
               sT0 = take(n), sT1 = take(n), sCx = take(50 * nix), sCy = take(50 * niy),
               sPart = take(4 * (size_t)nbd + 8), sMisc = take(16), sPc = take(np + 1),
-              sPw = take(np + 1);
+              sPw = take(np + 1), sTerms = take((size_t)N);
     if (tot > c->adj_doubles) {
         if (c->adj_mem) hipFree(c->adj_mem);
         c->adj_mem = nullptr;
@@ -677,13 +677,13 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     double* T0 = at(sT0);
     double* T1 = at(sT1);
     double* misc = at(sMisc);
+    double* terms = at(sTerms);   // loss term of every step
     int* dpc = (int*)at(sPc);
     double* dpw = at(sPw);
     if (np > 0) {
         HIPCHK(c, hipMemcpyAsync(dpc, pc, sizeof(int) * np, hipMemcpyHostToDevice, s), "probe copy");
         HIPCHK(c, hipMemcpyAsync(dpw, pw, sizeof(double) * np, hipMemcpyHostToDevice, s), "probe copy");
     }
-    HIPCHK(c, hipMemsetAsync(loss, 0, sizeof(double), s), "memset");
     HIPCHK(c, hipMemsetAsync(theta, 0, 2 * sizeof(double), s), "memset");
     HIPCHK(c, hipMemsetAsync(lam, 0, sizeof(double) * n5, s), "memset");
     // U0 from the primitives (the Q dependence of E0 is chained at the end)
@@ -715,17 +715,30 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
         return launch_stage(ONESTEP, 0, P->kind_mask, P->tile_w, a, 0, a.ntiles, q);
     };
     const double dt = tm->dt_fixed;
-    // ---- forward pass with checkpoints and the probe loss
+    // ---- forward pass with checkpoints; the last segment keeps its stage inputs
+    // (it is swept first and needs no recompute)
+    const int bl = (nseg - 1) & 1, nl0 = (nseg - 1) * K, ml = N - nl0;
+    double *L0 = S0b[bl], *L1 = S1b[bl], *L2 = S2b[bl];
     HIPCHK(c, entry(ck, s), "adjoint forward entry");
     HIPCHK(c, hipMemcpyAsync(T1, T0, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy");
     double* cur = ck;
     for (int step = 0; step < N; ++step) {
-        double* nxt = (step + 1 < N && (step + 1) % K == 0) ? ck + (size_t)((step + 1) / K) * n5
-                                                           : ((cur == S0) ? S0 + n5 : S0);
-        HIPCHK(c, stage(1, cur, cur, S1, s), "forward stage");
-        HIPCHK(c, stage(2, cur, S1, S2, s), "forward stage");
-        HIPCHK(c, stage(3, cur, S2, nxt, s), "forward stage");
-        HIPCHK(c, adj_loss_launch(ag, nxt, n, dpc, dpw, np, dt, loss, s), "loss");
+        if (step == nl0 && cur != L0) {
+            HIPCHK(c, hipMemcpyAsync(L0, cur, sizeof(double) * n5, hipMemcpyDeviceToDevice, s), "copy");
+            cur = L0;
+        }
+        const int m = step - nl0;
+        double *o1 = S1, *o2 = S2, *nxt;
+        if (m >= 0) {
+            o1 = L1 + (size_t)m * n5;
+            o2 = L2 + (size_t)m * n5;
+            nxt = L0 + (size_t)(m + 1) * n5;
+        } else {
+            nxt = ((step + 1) % K == 0) ? ck + (size_t)((step + 1) / K) * n5 : ((cur == S0) ? S0 + n5 : S0);
+        }
+        HIPCHK(c, stage(1, cur, cur, o1, s), "forward stage");
+        HIPCHK(c, stage(2, cur, o1, o2, s), "forward stage");
+        HIPCHK(c, stage(3, cur, o2, nxt, s), "forward stage");
         cur = nxt;
     }
     // ---- reverse sweep
@@ -750,8 +763,9 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     hipEvent_t evFwd = c->adj_ev[0], evRec[2] = {c->adj_ev[1], c->adj_ev[2]},
                evRev[2] = {c->adj_ev[3], c->adj_ev[4]};
     bool used[2] = {false, false};
-    // recompute segment sg into buffer b (auxiliary stream), storing the three
-    // stage inputs of every step, then alpha and its argmax of all of them
+    // recompute segment sg (< nseg - 1) into buffer b (auxiliary stream), storing
+    // the three stage inputs of every step, then alpha and its argmax of all of
+    // them and the segment's loss terms
     auto recompute = [&](int sg, int b) -> hipError_t {
         const int n0 = sg * K, m1 = std::min(N, n0 + K) - n0;
         double *R0 = S0b[b], *R1 = S1b[b], *R2 = S2b[b];
@@ -777,12 +791,29 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
         ap.alpha = at(sAlpha[b]);
         ap.argm = (int*)at(sArgm[b]);
         if (e == hipSuccess) e = adj_alpha_launch(ap, s2);
+        // loss terms of states n0 + 1 .. n0 + m1 (the last one is the next checkpoint)
+        if (e == hipSuccess)
+            e = adj_loss_launch(ag, R0, n5, m1, ck + (size_t)(sg + 1) * n5, n0, n, dpc, dpw, np, dt,
+                                terms, s2);
         if (e == hipSuccess) e = hipEventRecord(evRec[b], s2);
         return e;
     };
+    {   // the last segment: alpha of its stage inputs and its loss terms
+        AlphaArgs ap = AP;
+        ap.base[0] = L0;
+        ap.base[1] = L1;
+        ap.base[2] = L2;
+        ap.nsteps = ml;
+        ap.part = at(sApart[bl]);
+        ap.alpha = at(sAlpha[bl]);
+        ap.argm = (int*)at(sArgm[bl]);
+        HIPCHK(c, adj_alpha_launch(ap, s), "adjoint alpha");
+        HIPCHK(c, adj_loss_launch(ag, L0, n5, ml + 1, nullptr, nl0, n, dpc, dpw, np, dt, terms, s),
+               "loss");
+        HIPCHK(c, hipEventRecord(evRec[bl], s), "event");
+    }
     HIPCHK(c, hipEventRecord(evFwd, s), "event");
     HIPCHK(c, hipStreamWaitEvent(s2, evFwd, 0), "event");
-    HIPCHK(c, recompute(nseg - 1, (nseg - 1) & 1), "recompute");
     for (int sg = nseg - 1; sg >= 0; --sg) {
         const int b = sg & 1;
         const int n0 = sg * K, m1 = std::min(N, n0 + K) - n0;
@@ -813,6 +844,7 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
         HIPCHK(c, hipEventRecord(evRev[b], s), "event");
         used[b] = true;
     }
+    HIPCHK(c, adj_loss_sum_launch(terms, N, loss, s), "loss");
     // chain dL/dU0 to the primitives; E0 = p/(gamma-1) + rho |u|^2/2 + rho Y Q adds to dL/dQ
     HIPCHK(c, adj_chain_launch(ag, W0, lam, n, gW, A.part, theta, s), "chain");
     return JANC_OK;

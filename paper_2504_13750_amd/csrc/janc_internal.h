@@ -174,8 +174,10 @@ struct AlphaArgs {
 
 hipError_t adj_alpha_launch(const AlphaArgs& P, hipStream_t s);
 hipError_t adj_stage(const AdjArgs& A, hipStream_t s);
-hipError_t adj_loss_launch(const AdjGrid& g, const double* U, long long n, const int* pc,
-                           const double* pw, int np, double dt, double* loss, hipStream_t s);
+hipError_t adj_loss_launch(const AdjGrid& g, const double* base, long long stride, int count,
+                           const double* last, int n0, long long n, const int* pc, const double* pw,
+                           int np, double dt, double* term, hipStream_t s);
+hipError_t adj_loss_sum_launch(const double* term, int nsteps, double* loss, hipStream_t s);
 hipError_t adj_seed_launch(const AdjGrid& g, const double* U, long long n, const int* pc,
                            const double* pw, int np, double dt, double* lam, double* theta,
                            hipStream_t s);
