@@ -307,6 +307,10 @@ def main():
             "avg_launch_ms": stage_avg,
             "hbm_algorithmic_GBs": achieved_gbs,
             "hbm_frac": achieved_gbs / PEAK_HBM_GBS,
+            # max(t_HBM, t_VALU) / t_measured at the peaks: the bound that binds
+            "binding": "fp64-valu" if achieved_tf / PEAK_FP64_VALU_TFLOPS >=
+                       achieved_gbs / PEAK_HBM_GBS else "hbm",
+            "binding_frac": max(achieved_tf / PEAK_FP64_VALU_TFLOPS, achieved_gbs / PEAK_HBM_GBS),
         },
         "kernels_ms": {"stage": stage_avg, "chemistry": float(np.mean(chem_ms)),
                        "restriction": float(np.mean(restr_ms)), "ring": float(np.mean(ring_ms))},
