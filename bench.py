@@ -64,12 +64,15 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+STAGE_SOURCES = ("janc_device.h", "janc_internal.h", "janc_kernels.hip")
+
+
 def kernel_source_hash():
-    import glob
+    """sha256[:16] of the sources the stage kernel is compiled from."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2504_13750_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for f in STAGE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2504_13750_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -8,19 +8,22 @@
 //   lambda_Un += a lambda_W,  theta-gradient += (dL/dtheta)^T mu,
 // with L(V) = -dF/dx - dG/dy + S. The vector-Jacobian product (dL/dV)^T mu is
 // formed in gather form, without atomics on floating-point values:
-//   A0/A0b  alpha_x = max(|u|+c), alpha_y = max(|v|+c) and their argmax (lowest
-//           linear index among equal maxima) from the stage input;
-//   A1      per cell of the x and y strips (interior plus 3 ghost layers): the
-//           ghost source, the state, and the split fluxes F+/F- (G+/G-);
-//   B       per interface: mu_Fhat = (mu_right - mu_left)/dx and the reverse of
-//           both WENO5 reconstructions (5 + 5 weights per component);
-//   C       per strip cell: gather of the split-flux adjoints from the 5 + 5
-//           interfaces that read it, reverse of the split (flux Jacobian and
-//           the alpha term), partial sums of d/dalpha and of d/dQ;
-//   D       per interior cell: own strip values, ghost cells that copy or mirror
-//           it, the explicit Arrhenius source, and the RK bookkeeping;
-//   E       one workgroup: the deterministic sums of the partials, the alpha
-//           adjoints applied at the argmax cells, theta accumulation.
+//   A  (once per checkpoint segment, every stage input of the segment)
+//      alpha_x = max(|u|+c), alpha_y = max(|v|+c) and their argmax (lowest
+//      linear index among equal maxima): block maxima, then one workgroup per
+//      stage input;
+//   B  per interface and component: mu_Fhat = b dt (mu_right - mu_left)/dx and
+//      the reverse of both WENO5 reconstructions (5 + 5 weights), the six
+//      stencil states and their split fluxes formed in place;
+//   C  per interior cell (x and y sweeps on two threads): gather of the
+//      split-flux adjoints of its own strip positions and of the ghost positions
+//      that copy or mirror it from the 5 + 5 interfaces that read them, reverse
+//      of the split (flux Jacobian and the alpha term), the explicit Arrhenius
+//      source, the RK bookkeeping, block partials of d/dalpha, d/dQ, d/dEa;
+//   D  one workgroup: the partials summed in a fixed order, the alpha adjoints
+//      applied at the argmax cells, theta, and the loss seed of the step start.
+// Every thread issues its loads together (clamped indices, masked afterwards):
+// the small grids of an adjoint run are bound by memory latency, not bandwidth.
 #include "janc_device.h"
 
 namespace janc {
@@ -28,8 +31,6 @@ namespace janc {
 constexpr int NU5 = 5;
 constexpr int AWG = 256;
 
-__host__ __device__ __forceinline__ int xs_n(const AdjGrid& g) { return (g.nx + 6) * g.ny; }
-__host__ __device__ __forceinline__ int ys_n(const AdjGrid& g) { return g.twod ? g.nx * (g.ny + 6) : 0; }
 
 // Source of grid position (i, j) (one coordinate may lie in the 3 ghost layers).
 __device__ long long usrc(const AdjGrid& g, int i, int j, unsigned& fl) {
