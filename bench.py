@@ -120,6 +120,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-block", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-crossover", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
@@ -162,11 +163,12 @@ def main():
         T.copy_(tt)
         return U, T, torch.zeros(1, dtype=torch.float64, device=dev)
 
-    def timed_run(plan, steps, warmup):
+    def timed_run(plan, steps, warmup, sim=None):
         U, T, t = fresh_state()
         if warmup:
             ctx.step_blocks(plan, tm, U, T, warmup, t)
         ctx.sync_status()
+        t_start = float(t[0].item())
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
@@ -176,13 +178,16 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         ctx.sync_status()
+        if sim is not None:
+            sim.append(float(t[0].item()) - t_start)   # simulated time of the timed steps
         return e0.elapsed_time(e1) / 1e3, wall, (U, T, t)
 
     # ------------------------------------------------------------ fused batched form
     log(f"[bench] fused batched step: {len(case.blocks)} blocks, {cells} cells, "
         f"{args.warmup} warm-up + {args.steps} timed steps")
     plan = ctx.plan(domains, case.blocks, case.pool_cells, janc.PLAN_DEFAULT)
-    gpu_s, wall_s, (U, T, t) = timed_run(plan, args.steps, args.warmup)
+    sim_sync = []
+    gpu_s, wall_s, (U, T, t) = timed_run(plan, args.steps, args.warmup, sim_sync)
     value = cells * 3 * args.steps / gpu_s
     ms_step = 1e3 * gpu_s / args.steps
     log(f"[bench] {ms_step:.3f} ms/step, {value:.4e} cell-stage/s (wall {wall_s:.3f} s)")
@@ -224,6 +229,30 @@ def main():
         log(f"[bench] per-block form {per_block['ms_per_step']:.3f} ms/step "
             f"-> fused speed-up {value / pb_value:.2f}x")
         pplan.close()
+
+    # ------------------------------------------------------------ crossover advance
+    crossover = None
+    if not args.no_crossover:
+        xplan = ctx.plan(domains, case.blocks, case.pool_cells, janc.PLAN_CROSSOVER)
+        xsteps = max(1, args.steps // 4)
+        sim_x = []
+        x_s, _, _ = timed_run(xplan, xsteps, 1, sim_x)
+        lev_cells = {}
+        for b in case.blocks:
+            if b["valid"]:
+                lev_cells[int(b["level"])] = lev_cells.get(int(b["level"]), 0) + int(b["nx"] * b["ny"])
+        x_updates = sum(n * (1 << l) for l, n in lev_cells.items()) * 3 * xsteps
+        rate_x = sim_x[0] / x_s
+        rate_s = sim_sync[0] / gpu_s
+        crossover = {"ms_per_step": 1e3 * x_s / xsteps, "steps": xsteps,
+                     "cell_stage_per_s": x_updates / x_s,
+                     "simulated_time_per_s": rate_x,
+                     "synchronous_simulated_time_per_s": rate_s,
+                     "speedup_vs_synchronous": rate_x / rate_s,
+                     "form": "Fig. 2a: per level dt_0/2^l, deepest level first"}
+        log(f"[bench] crossover advance {crossover['ms_per_step']:.3f} ms per level-0 step, "
+            f"{rate_x / rate_s:.2f}x the synchronous advance in simulated time per second")
+        xplan.close()
 
     # ------------------------------------------------------------ adjoint / forward cost
     adjoint = None
@@ -318,6 +347,7 @@ def main():
         "kernels_ms": {"stage": stage_avg, "chemistry": float(np.mean(chem_ms)),
                        "restriction": float(np.mean(restr_ms)), "ring": float(np.mean(ring_ms))},
         "per_block": per_block,
+        "crossover": crossover,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
         "context": "paper (A100, real H2-O2 mechanism, 2.76 M cells incl. invalid blocks): "

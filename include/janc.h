@@ -8,8 +8,8 @@
  * reconstruction with 3 ghost layers, the conservative difference (Eq. 4.10),
  * third-order TVD Runge-Kutta, Newton for T from the internal energy, and the
  * first-order point-implicit chemistry step (Eq. 4.12-4.13). Block tables carry
- * the block-structured AMR of Sec. 3 (synchronous advance, Fig. 2b) and
- * ensembles of independent problems.
+ * the block-structured AMR of Sec. 3 (synchronous advance, Fig. 2b, or the
+ * crossover advance, Fig. 2a) and ensembles of independent problems.
  *
  * Conventions for every call:
  *   - Arrays marked (device) are FP64 device memory owned by the caller; arrays
@@ -129,7 +129,8 @@ janc_status janc_step(janc_ctx *ctx, const janc_grid *grid, const janc_physics *
 /* ------------------------------------------------------------------ block tables */
 /* A domain is one independent problem: a level-0 grid, its boundaries, its
  * physics and the number of refinement levels (ratio 2, Sec. 3.1). Each domain
- * has its own dt; all levels of a domain share it (synchronous advance, Fig. 2b). */
+ * has its own dt: in the synchronous advance (Fig. 2b) all its levels share it;
+ * in the crossover advance (Fig. 2a) level l uses dt_0 / 2^l. */
 typedef struct {
     janc_grid grid;
     janc_physics phys;
@@ -151,7 +152,8 @@ typedef struct janc_plan janc_plan;
 enum {
     JANC_PLAN_DEFAULT = 0,
     JANC_PLAN_PER_BLOCK = 1,   /* one launch per block and stage (comparison form) */
-    JANC_PLAN_NO_GRAPH = 2     /* launch kernels directly instead of a captured hipGraph */
+    JANC_PLAN_NO_GRAPH = 2,    /* launch kernels directly instead of a captured hipGraph */
+    JANC_PLAN_CROSSOVER = 4    /* crossover advance (Fig. 2a, Alg. 2) instead of the synchronous one */
 };
 
 /* Validate a block table and build its device work lists (blocks, level maps,
@@ -171,12 +173,18 @@ janc_status janc_plan_stats(const janc_plan *plan, long long *out);
  * for 2-D blocks (16 or 32 or 64; height = 256 / width). Synchronous. */
 janc_status janc_plan_set_tile(janc_plan *plan, int tile_width);
 
-/* nsteps steps over a block table (Alg. 2 with synchronous advance and Alg. 3
- * per stage): per domain dt; per (domain, level) alpha; ring cells of levels >= 1
- * take the coarser level's value at the same stage; after each step coarse
- * cells under finer blocks become the mean of their four children (finest level
- * first) and ring cells are refilled. U_pool (device) [nfields][pool],
- * T_pool (device) [pool], t (device) [ndomains]. */
+/* nsteps steps over a block table (Alg. 2 and Alg. 3 per stage): per domain dt;
+ * per (domain, level) alpha; after each step coarse cells under finer blocks
+ * become the mean of their four children (finest level first) and ring cells
+ * are refilled. Synchronous advance (default): every level takes each RK stage
+ * together with dt = CFL / max over all levels of (|u|+c)/dx_l + (|v|+c)/dy_l;
+ * ring cells of levels >= 1 take the coarser level's value at the same stage.
+ * Crossover advance (JANC_PLAN_CROSSOVER): a step is one step of level 0 with
+ * dt_0 = CFL / max over all levels of (|u|+c)/dx_0 + (|v|+c)/dy_0; before each
+ * step of level l, level l + 1 takes two steps of dt_0 / 2^(l+1) (deepest level
+ * first), reading its ring and uncovered halo cells from the coarser level's
+ * current state. U_pool (device) [nfields][pool], T_pool (device) [pool],
+ * t (device) [ndomains]. */
 janc_status janc_step_blocks(janc_ctx *ctx, janc_plan *plan, const janc_time *time,
                              double *U_pool, double *T_pool, int nsteps, double *t,
                              void *stream);
@@ -186,7 +194,7 @@ janc_status janc_step_blocks(janc_ctx *ctx, janc_plan *plan, const janc_time *ti
  * `stream` around each launch group. ms (host) [6] receives the durations in
  * milliseconds of RK stage 1, stage 2, stage 3, the chemistry step, the
  * restriction (all levels) and the ring refill. U_pool, T_pool and t advance by
- * the step. Synchronizes the stream. */
+ * the step. Synchronizes the stream. Crossover plans return JANC_EINVAL. */
 janc_status janc_profile_step(janc_ctx *ctx, janc_plan *plan, const janc_time *time,
                               double *U_pool, double *T_pool, double *t, double *ms,
                               void *stream);

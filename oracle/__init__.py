@@ -229,8 +229,12 @@ def block_state(bcase):
     return U, T
 
 
-def step_blocks(bcase, U, T, nsteps, t=None, cfl=None, dt_fixed=None, t_end=None, check=True):
-    """Advance a block table nsteps; returns (U, T, t[ndom], dt_log[nsteps, ndom], status)."""
+def step_blocks(bcase, U, T, nsteps, t=None, cfl=None, dt_fixed=None, t_end=None, check=True,
+                crossover=False):
+    """Advance a block table nsteps; returns (U, T, t[ndom], dt_log[nsteps, ndom], status).
+
+    crossover=False: synchronous advance (paper Fig. 2b); True: crossover advance (Fig. 2a,
+    Alg. 2), where a step is one level-0 step (dt_log holds dt_0)."""
     U = _f64(U).copy()
     T = _f64(T).copy()
     nd = len(bcase.domains)
@@ -249,7 +253,7 @@ def step_blocks(bcase, U, T, nsteps, t=None, cfl=None, dt_fixed=None, t_end=None
     st = lib().oracle_step_blocks(I(bcase.model), mv.ptr, I(nd), doms, _p(bp), I(len(blocks)),
                                   blocks.ctypes.data_as(C.c_void_p),
                                   C.c_longlong(bcase.pool_cells), C.byref(tm), _p(U), _p(T),
-                                  I(nsteps), _p(tt), _p(dts))
+                                  I(nsteps), _p(tt), _p(dts), I(1 if crossover else 0))
     if check:
         _check(st, "step_blocks")
     return U, T, tt, dts[:nsteps], st

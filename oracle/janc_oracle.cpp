@@ -24,7 +24,8 @@
  *   first-order point-implicit chemistry on rho Y_1..rho Y_{Ns-1}    (Eq. 4.12-4.13)
  *   mass-action rates with Arrhenius forward and equilibrium reverse (Eq. 4.6-4.9)
  *   block tables: same-level ghosts, coarse-fine "external boundary" sync,
- *   four-to-one restriction, synchronous advance                     (Sec. 3.1.3-3.1.4, Alg. 2-3)
+ *   four-to-one restriction, synchronous and crossover advance       (Sec. 3.1.3-3.1.4, Alg. 2-3,
+ *                                                                     Fig. 2)
  *
  * Readings where the paper is silent (also listed in the design doc):
  *   - WENO5 is the Jiang-Shu form with eps = 1e-6, applied component-wise.
@@ -816,6 +817,7 @@ struct Src {
     long long cell = -1;   // pool cell, or -1 for a Dirichlet state
     int side = -1;         // Dirichlet side
     int negx = 0, negy = 0;
+    int level = -1;        // level of the source cell
 };
 
 // Effective value of level-l cell (I, J): boundary rule, then the same-level
@@ -852,6 +854,7 @@ int resolve(const BlockSet& B, int d, int l, int I, int J, Src& s) {
             int li = I - r.i0, lj = J - r.j0;
             if (!B.ring[b][(size_t)lj * r.nx + li]) {
                 s.cell = r.offset + (long long)lj * r.nx + li;
+                s.level = l;
                 return ST_OK;
             }
         }
@@ -875,6 +878,85 @@ void load_src(const BlockSet& B, int d, const Src& s, const std::vector<std::vec
     if (s.negx) out[1] = -out[1];
     if (s.negy) out[2] = -out[2];
     Tout = T[s.cell];
+}
+
+// Four-to-one restriction finest level first (Alg. 2 interpolate_fine_to_coarse), then
+// the ring cells of every refined level take the injection of the restricted coarser
+// level. Domains whose dt is 0 are left alone.
+template <class S>
+int restrict_and_refill(const BlockSet& B, const std::vector<Phys<S>>& phys,
+                        const std::vector<std::vector<S>>& bcU, const std::vector<S>& bcT,
+                        std::vector<S>& Uout, std::vector<S>& Tout, const std::vector<S>& dt) {
+    const int nU = B.nU;
+    const long long pool = B.pool;
+    const int nd = (int)B.dom.size(), nb = (int)B.blk.size();
+    auto solved = [&](int b, int i, int j) { return !B.ring[b][(size_t)j * B.blk[b].nx + i]; };
+    // restriction, finest level first: a covered coarse cell becomes the mean of its 4 children
+    int maxlev = 0;
+    for (int d = 0; d < nd; ++d) maxlev = std::max(maxlev, B.dom[d].nlevels - 1);
+    for (int lev = maxlev; lev >= 1; --lev) {
+        struct Upd { long long cell; int dom; std::vector<S> u; };
+        std::vector<Upd> upd;
+        for (int b = 0; b < nb; ++b) {
+            const BlockRec& r = B.blk[b];
+            if (!r.valid || r.level != lev) continue;
+            const int d = r.domain;
+            if (!(val(dt[d]) > 0.0)) continue;
+            const DomainGeo& G = B.geo[d];
+            int cw = G.lw[lev - 1];
+            for (int cj = r.j0 / 2; cj < (r.j0 + r.ny) / 2; ++cj)
+                for (int ci = r.i0 / 2; ci < (r.i0 + r.nx) / 2; ++ci) {
+                    S ch[4][64];
+                    S Tch;
+                    for (int q = 0; q < 4; ++q) {
+                        Src s;
+                        if (resolve(B, d, lev, 2 * ci + (q & 1), 2 * cj + (q >> 1), s)) return ST_EINVAL;
+                        load_src(B, d, s, bcU, bcT, Uout.data(), Tout.data(), pool, ch[q], Tch);
+                    }
+                    Upd u;
+                    int cb = G.cover[lev - 1][(size_t)cj * cw + ci];
+                    const BlockRec& cr = B.blk[cb];
+                    u.cell = cr.offset + (long long)(cj - cr.j0) * cr.nx + (ci - cr.i0);
+                    u.dom = d;
+                    u.u.resize(nU);
+                    for (int f = 0; f < nU; ++f)
+                        u.u[f] = ((ch[0][f] + ch[1][f]) + (ch[2][f] + ch[3][f])) * 0.25;
+                    upd.push_back(u);
+                }
+        }
+        // all means are formed from pre-restriction values before any coarse cell changes
+        for (size_t q = 0; q < upd.size(); ++q) {
+            long long c = upd[q].cell;
+            for (int f = 0; f < nU; ++f) Uout[(size_t)f * pool + c] = upd[q].u[f];
+        }
+        // T of restricted cells is re-solved, warm-started from the coarse cell's T
+        for (size_t q = 0; q < upd.size(); ++q) {
+            long long c = upd[q].cell;
+            S Tn = 0.0;
+            int st = cell_temperature(phys[upd[q].dom], upd[q].u.data(), Tout[c], Tn);
+            if (st) return st;
+            Tout[c] = Tn;
+        }
+    }
+    // ring cells take the injection of the (restricted) coarser level
+    for (int lev = 1; lev <= maxlev; ++lev) {
+        for (int b = 0; b < nb; ++b) {
+            const BlockRec& r = B.blk[b];
+            if (!r.valid || r.level != lev || !(val(dt[r.domain]) > 0.0)) continue;
+            for (int j = 0; j < r.ny; ++j)
+                for (int i = 0; i < r.nx; ++i) {
+                    if (solved(b, i, j)) continue;
+                    Src s;
+                    if (resolve(B, r.domain, lev - 1, (r.i0 + i) >> 1, (r.j0 + j) >> 1, s)) return ST_EINVAL;
+                    S u[64], Tv;
+                    load_src(B, r.domain, s, bcU, bcT, Uout.data(), Tout.data(), pool, u, Tv);
+                    long long c = r.offset + (long long)j * r.nx + i;
+                    for (int f = 0; f < nU; ++f) Uout[(size_t)f * pool + c] = u[f];
+                    Tout[c] = Tv;
+                }
+        }
+    }
+    return ST_OK;
 }
 
 template <class S>
@@ -1043,74 +1125,196 @@ int step_blocks(BlockSet& B, const std::vector<Phys<S>>& phys, const TimeCfg& tc
         }
         if (status) return status;
     }
-    // restriction, finest level first: a covered coarse cell becomes the mean of its 4 children
-    int maxlev = 0;
-    for (int d = 0; d < nd; ++d) maxlev = std::max(maxlev, B.dom[d].nlevels - 1);
-    for (int lev = maxlev; lev >= 1; --lev) {
-        struct Upd { long long cell; int dom; std::vector<S> u; };
-        std::vector<Upd> upd;
-        for (int b = 0; b < nb; ++b) {
-            const BlockRec& r = B.blk[b];
-            if (!r.valid || r.level != lev) continue;
-            const int d = r.domain;
-            if (!(val(dt[d]) > 0.0)) continue;
-            const DomainGeo& G = B.geo[d];
-            int cw = G.lw[lev - 1];
-            for (int cj = r.j0 / 2; cj < (r.j0 + r.ny) / 2; ++cj)
-                for (int ci = r.i0 / 2; ci < (r.i0 + r.nx) / 2; ++ci) {
-                    S ch[4][64];
-                    S Tch;
-                    for (int q = 0; q < 4; ++q) {
-                        Src s;
-                        if (resolve(B, d, lev, 2 * ci + (q & 1), 2 * cj + (q >> 1), s)) return ST_EINVAL;
-                        load_src(B, d, s, bcU, bcT, Uout.data(), Tout.data(), pool, ch[q], Tch);
-                    }
-                    Upd u;
-                    int cb = G.cover[lev - 1][(size_t)cj * cw + ci];
-                    const BlockRec& cr = B.blk[cb];
-                    u.cell = cr.offset + (long long)(cj - cr.j0) * cr.nx + (ci - cr.i0);
-                    u.dom = d;
-                    u.u.resize(nU);
-                    for (int f = 0; f < nU; ++f)
-                        u.u[f] = ((ch[0][f] + ch[1][f]) + (ch[2][f] + ch[3][f])) * 0.25;
-                    upd.push_back(u);
-                }
-        }
-        // all means are formed from pre-restriction values before any coarse cell changes
-        for (size_t q = 0; q < upd.size(); ++q) {
-            long long c = upd[q].cell;
-            for (int f = 0; f < nU; ++f) Uout[(size_t)f * pool + c] = upd[q].u[f];
-        }
-        // T of restricted cells is re-solved, warm-started from the coarse cell's T
-        for (size_t q = 0; q < upd.size(); ++q) {
-            long long c = upd[q].cell;
-            S Tn = 0.0;
-            int st = cell_temperature(phys[upd[q].dom], upd[q].u.data(), Tout[c], Tn);
-            if (st) return st;
-            Tout[c] = Tn;
-        }
-    }
-    // ring cells take the injection of the (restricted) coarser level
-    for (int lev = 1; lev <= maxlev; ++lev) {
-        for (int b = 0; b < nb; ++b) {
-            const BlockRec& r = B.blk[b];
-            if (!r.valid || r.level != lev || !(val(dt[r.domain]) > 0.0)) continue;
-            for (int j = 0; j < r.ny; ++j)
-                for (int i = 0; i < r.nx; ++i) {
-                    if (solved(b, i, j)) continue;
-                    Src s;
-                    if (resolve(B, r.domain, lev - 1, (r.i0 + i) >> 1, (r.j0 + j) >> 1, s)) return ST_EINVAL;
-                    S u[64], Tv;
-                    load_src(B, r.domain, s, bcU, bcT, Uout.data(), Tout.data(), pool, u, Tv);
-                    long long c = r.offset + (long long)j * r.nx + i;
-                    for (int f = 0; f < nU; ++f) Uout[(size_t)f * pool + c] = u[f];
-                    Tout[c] = Tv;
-                }
-        }
-    }
+    status = restrict_and_refill(B, phys, bcU, bcT, Uout, Tout, dt);
+    if (status) return status;
     Upool.swap(Uout);
     Tpool.swap(Tout);
     for (int d = 0; d < nd; ++d) t[d] += val(dt[d]);
+    return ST_OK;
+}
+
+// Wave-speed maxima over the solved cells of the valid blocks of one level (all levels
+// when lev < 0) of a state: alpha_x, alpha_y per (domain, level) (Eq. 4.11) and the
+// per-domain CFL bound max((|u|+c)/dx + (|v|+c)/dy), with the spacing of level 0 when
+// spacing0 is set, else each block's own level spacing.
+template <class S>
+int level_maxima(const BlockSet& B, const std::vector<Phys<S>>& phys, const S* Us, const S* Ts,
+                 int lev, bool spacing0, std::vector<S>& ax, std::vector<S>& ay,
+                 std::vector<S>& cm) {
+    const int nU = B.nU, nd = (int)B.dom.size(), nb = (int)B.blk.size();
+    const long long pool = B.pool;
+    const int L = 8;
+    ax.assign((size_t)nd * L, S(0.0));
+    ay.assign((size_t)nd * L, S(0.0));
+    cm.assign(nd, S(0.0));
+    for (int b = 0; b < nb; ++b) {
+        const BlockRec& r = B.blk[b];
+        if (!r.valid || (lev >= 0 && r.level != lev)) continue;
+        const DomainRec& D = B.dom[r.domain];
+        const int sl = spacing0 ? 0 : r.level;
+        const double dxl = D.dx / (1 << sl), dyl = D.dy / (1 << sl);
+        const int slot = r.domain * L + r.level;
+        for (int j = 0; j < r.ny; ++j)
+            for (int i = 0; i < r.nx; ++i) {
+                if (B.ring[b][(size_t)j * r.nx + i]) continue;
+                const long long c = r.offset + (long long)j * r.nx + i;
+                S u[64];
+                for (int f = 0; f < nU; ++f) u[f] = Us[(size_t)f * pool + c];
+                Prim<S> P;
+                const int st = primitives(phys[r.domain], u, Ts[c], P);
+                if (st) return st;
+                const S sx = fabs(P.u) + P.c, sy = fabs(P.v) + P.c;
+                const S sc = sx / dxl + ((D.ny > 1) ? sy / dyl : S(0.0));
+                if (val(sx) > val(ax[slot])) ax[slot] = sx;
+                if (val(sy) > val(ay[slot])) ay[slot] = sy;
+                if (val(sc) > val(cm[r.domain])) cm[r.domain] = sc;
+            }
+    }
+    return ST_OK;
+}
+
+// One step of the crossover advance (Fig. 2a, Alg. 2): the deepest level first; every
+// two steps of a level are followed by one step of the next coarser level, and each
+// level's time step is half that of the coarser one, dt_l = dt_0 / 2^l. dt_0 keeps every
+// level within the CFL bound: dt_0 = CFL / max over all levels' solved cells of
+// (|u|+c)/dx_0 + (|v|+c)/dy_0. While a level advances, the coarser levels hold their
+// current states: halo cells of the level that are uncovered there, and its ring cells,
+// take the injection of that current coarser state at every RK stage. After the level-0
+// step every level is at t + dt_0; then the four-to-one restriction and the ring refill
+// of the synchronous advance.
+template <class S>
+int step_blocks_crossover(BlockSet& B, const std::vector<Phys<S>>& phys, const TimeCfg& tc,
+                          const std::vector<std::vector<S>>& bcU, const std::vector<S>& bcT,
+                          std::vector<S>& Upool, std::vector<S>& Tpool, std::vector<double>& t,
+                          double* dt_out) {
+    const int nU = B.nU;
+    const long long pool = B.pool;
+    const int nd = (int)B.dom.size(), nb = (int)B.blk.size();
+    std::vector<S> ax, ay, cm;
+    int status = level_maxima(B, phys, Upool.data(), Tpool.data(), -1, true, ax, ay, cm);
+    if (status) return status;
+    std::vector<S> dt0(nd);
+    for (int d = 0; d < nd; ++d) {
+        choose_dt(tc, cm[d], t[d], dt0[d]);
+        if (dt_out) dt_out[d] = val(dt0[d]);
+    }
+    int maxlev = 0;
+    for (int d = 0; d < nd; ++d) maxlev = std::max(maxlev, B.dom[d].nlevels - 1);
+    std::vector<S> U1((size_t)pool * nU), U2((size_t)pool * nU), T1(pool), T2(pool);
+
+    // one RK3 step (and chemistry) of the blocks of level lev, time step dt_0 / 2^lev
+    auto advance_level = [&](int lev) -> int {
+        std::vector<S> dtl(nd);
+        for (int d = 0; d < nd; ++d) dtl[d] = dt0[d] * std::ldexp(1.0, -lev);
+        std::vector<S> Unew = Upool, Tnew = Tpool;
+        const std::vector<S>* Uin = &Upool;
+        const std::vector<S>* Tin = &Tpool;
+        for (int stage = 1; stage <= 3; ++stage) {
+            int st = level_maxima(B, phys, Uin->data(), Tin->data(), lev, false, ax, ay, cm);
+            if (st) return st;
+            std::vector<S>& Udst = (stage == 1) ? U1 : (stage == 2) ? U2 : Unew;
+            std::vector<S>& Tdst = (stage == 1) ? T1 : (stage == 2) ? T2 : Tnew;
+            int status2 = ST_OK;
+#pragma omp parallel for schedule(dynamic)
+            for (int b = 0; b < nb; ++b) {
+                const BlockRec& r = B.blk[b];
+                if (!r.valid || r.level != lev) continue;
+                const int d = r.domain;
+                if (!(val(dtl[d]) > 0.0)) {
+                    for (long long c = r.offset; c < r.offset + (long long)r.nx * r.ny; ++c) {
+                        for (int f = 0; f < nU; ++f) Udst[(size_t)f * pool + c] = (*Uin)[(size_t)f * pool + c];
+                        Tdst[c] = (*Tin)[c];
+                    }
+                    continue;
+                }
+                const Phys<S>& ph = phys[d];
+                const DomainRec& D = B.dom[d];
+                Ext<S> E;
+                E.init(nU, r.nx, (D.ny > 1) ? r.ny : 1);
+                int st2 = ST_OK;
+                for (int j = -E.gy; j < r.ny + E.gy && !st2; ++j)
+                    for (int i = -E.g; i < r.nx + E.g && !st2; ++i) {
+                        if (!E.in_cross(i, j)) continue;
+                        Src sr;
+                        st2 = resolve(B, d, lev, r.i0 + i, r.j0 + j, sr);
+                        if (st2) break;
+                        // this level's cells at the stage; coarser levels at their current state
+                        const bool same = sr.cell >= 0 && sr.level == lev;
+                        load_src(B, d, sr, bcU, bcT, same ? Uin->data() : Upool.data(),
+                                 same ? Tin->data() : Tpool.data(), pool, E.u(i, j), E.t(i, j));
+                    }
+                std::vector<S> L;
+                const int slot = d * 8 + lev;
+                if (!st2) st2 = rhs_ext(ph, E, ax[slot], ay[slot], D.dx / (1 << lev),
+                                        D.dy / (1 << lev), L);
+                if (!st2) {
+                    for (int j = 0; j < r.ny && !st2; ++j)
+                        for (int i = 0; i < r.nx && !st2; ++i) {
+                            if (B.ring[b][(size_t)j * r.nx + i]) continue;
+                            const long long c = r.offset + (long long)j * r.nx + i;
+                            S un[64];
+                            for (int f = 0; f < nU; ++f) {
+                                const S u0 = Upool[(size_t)f * pool + c];
+                                const S us = (*Uin)[(size_t)f * pool + c];
+                                un[f] = rk_combine(stage, u0, us, L[((size_t)j * r.nx + i) * nU + f], dtl[d]);
+                                Udst[(size_t)f * pool + c] = un[f];
+                            }
+                            S Tn = 0.0;
+                            st2 = cell_temperature(ph, un, (*Tin)[c], Tn);
+                            Tdst[c] = Tn;
+                        }
+                }
+                if (st2) {
+#pragma omp critical
+                    status2 = st2;
+                }
+            }
+            if (status2) return status2;
+            Uin = &Udst;
+            Tin = &Tdst;
+        }
+        int status3 = ST_OK;
+#pragma omp parallel for schedule(dynamic)
+        for (int b = 0; b < nb; ++b) {
+            const BlockRec& r = B.blk[b];
+            if (!r.valid || r.level != lev || !(val(dtl[r.domain]) > 0.0)) continue;
+            for (int j = 0; j < r.ny; ++j)
+                for (int i = 0; i < r.nx; ++i) {
+                    if (B.ring[b][(size_t)j * r.nx + i]) continue;
+                    const long long c = r.offset + (long long)j * r.nx + i;
+                    S u[64];
+                    for (int f = 0; f < nU; ++f) u[f] = Unew[(size_t)f * pool + c];
+                    if (phys[r.domain].model == MODEL_DETAILED) {
+                        const int st = cell_chemistry(phys[r.domain], u, Tnew[c], dtl[r.domain]);
+                        if (st) {
+#pragma omp critical
+                            status3 = st;
+                        }
+                    }
+                    for (int f = 0; f < nU; ++f) Upool[(size_t)f * pool + c] = u[f];
+                    Tpool[c] = Tnew[c];
+                }
+        }
+        return status3;
+    };
+    // the recursion of Alg. 2: two steps of level l + 1, then one of level l
+    struct Rec {
+        decltype(advance_level)& adv;
+        int maxlev;
+        int run(int l) {
+            if (l < maxlev) {
+                int st = run(l + 1);
+                if (!st) st = run(l + 1);
+                if (st) return st;
+            }
+            return adv(l);
+        }
+    } rec{advance_level, maxlev};
+    status = rec.run(0);
+    if (status) return status;
+    status = restrict_and_refill(B, phys, bcU, bcT, Upool, Tpool, dt0);
+    if (status) return status;
+    for (int d = 0; d < nd; ++d) t[d] += val(dt0[d]);
     return ST_OK;
 }
 
@@ -1341,11 +1545,12 @@ int oracle_step(const OGrid* g, const OPhys* p, const OMech* m, const double* bc
 struct ODomain { int nx, ny; double dx, dy; int bc[4]; int nlevels; double gamma, R, Q, Ea, k; };
 
 // nsteps steps over a block table (pool SoA [nU][pool]); t_dom[ndom] advanced per domain;
-// dt_log [nsteps][ndom] (optional).
+// dt_log [nsteps][ndom] (optional); crossover = 0: synchronous advance (Fig. 2b), 1: the
+// crossover advance (Fig. 2a), where one step is one level-0 step.
 int oracle_step_blocks(int model, const OMech* m, int ndom, const ODomain* doms,
                        const double* bc_prim /* [ndom][4][nU] */, int nblocks,
                        const BlockRec* blocks, long long pool, const OTime* tm, double* U,
-                       double* T, int nsteps, double* t_dom, double* dt_log) {
+                       double* T, int nsteps, double* t_dom, double* dt_log, int crossover) {
     MechData md = mech_from(m);
     BlockSet B;
     B.pool = pool;
@@ -1389,8 +1594,9 @@ int oracle_step_blocks(int model, const OMech* m, int ndom, const ODomain* doms,
     std::vector<double> t(t_dom, t_dom + ndom);
     std::vector<double> dts(ndom);
     for (int s = 0; s < nsteps && !st; ++s) {
-        st = step_blocks(B, phys, TimeCfg{tm->cfl, tm->dt_fixed, tm->t_end}, bcU, bcT, Up, Tp, t,
-                         dts.data());
+        const TimeCfg tc{tm->cfl, tm->dt_fixed, tm->t_end};
+        st = crossover ? step_blocks_crossover(B, phys, tc, bcU, bcT, Up, Tp, t, dts.data())
+                       : step_blocks(B, phys, tc, bcU, bcT, Up, Tp, t, dts.data());
         if (dt_log)
             for (int d = 0; d < ndom; ++d) dt_log[(size_t)s * ndom + d] = dts[d];
     }

@@ -19,7 +19,7 @@ from ._lib import LibraryMissing
 
 CPG, ONESTEP, DETAILED = 0, 1, 2
 BC_PERIODIC, BC_ZEROGRAD, BC_SLIPWALL, BC_DIRICHLET = 0, 1, 2, 3
-PLAN_DEFAULT, PLAN_PER_BLOCK, PLAN_NO_GRAPH = 0, 1, 2
+PLAN_DEFAULT, PLAN_PER_BLOCK, PLAN_NO_GRAPH, PLAN_CROSSOVER = 0, 1, 2, 4
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONFINITE", -5: "ENEWTON",
           -6: "ENEGATIVE"}
 

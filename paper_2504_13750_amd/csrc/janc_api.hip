@@ -64,6 +64,7 @@ struct janc_plan {
     std::vector<int> hmap;
     std::vector<Tile> htiles;
     std::vector<int> tile_first, tile_count;   // per valid block
+    std::vector<int> lev_first, lev_count;     // per level: tiles (grouped by level)
     std::vector<std::vector<int>> fine;        // per level >= 1: valid block ids
     std::vector<int> ring_blocks;
     std::vector<double> hdir;
@@ -199,6 +200,10 @@ janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, con
         return fail(c, JANC_EINVAL, "empty block table");
     std::unique_ptr<janc_plan, void (*)(janc_plan*)> P(new janc_plan(), plan_free);
     P->ctx = c;
+    if (flags & ~(JANC_PLAN_PER_BLOCK | JANC_PLAN_NO_GRAPH | JANC_PLAN_CROSSOVER))
+        return fail(c, JANC_EINVAL, "unknown plan flags");
+    if ((flags & JANC_PLAN_PER_BLOCK) && (flags & JANC_PLAN_CROSSOVER))
+        return fail(c, JANC_EINVAL, "the crossover advance has no per-block form");
     P->flags = flags;
     P->ndom = nd;
     P->pool = pool;
@@ -405,7 +410,8 @@ janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, con
     if ((st = upload(c, &P->dfine, fl))) return st;
     if ((st = upload(c, &P->dring, P->ring_blocks))) return st;
     P->red_stride = 2 * P->nunits + nd;
-    if ((st = dalloc(c, &P->dred, (size_t)3 * P->red_stride))) return st;
+    const int ntrip = (flags & JANC_PLAN_CROSSOVER) ? P->maxlev + 1 : 1;   // slot triples
+    if ((st = dalloc(c, &P->dred, (size_t)3 * ntrip * P->red_stride))) return st;
     if ((st = dalloc(c, &P->ddt, nd))) return st;
     if ((st = dalloc(c, &P->dstep, 1))) return st;
     if ((st = dalloc(c, &P->U1, (size_t)nU * pool))) return st;
@@ -416,25 +422,33 @@ janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, con
     return JANC_OK;
 }
 
-// Tiles of every valid block for the plan's 2-D tile width (1-D blocks: 256-cell rows).
+// Tiles of every valid block for the plan's 2-D tile width (1-D blocks: 256-cell rows),
+// grouped by level (the crossover advance launches one level at a time).
 janc_status build_tiles(janc_ctx* c, janc_plan* P) {
     P->htiles.clear();
     P->tile_first.assign(P->nblk, 0);
     P->tile_count.assign(P->nblk, 0);
+    P->lev_first.assign(P->maxlev + 1, 0);
+    P->lev_count.assign(P->maxlev + 1, 0);
     P->kind_mask = 0;
     const int TX = P->tile_w, TY = 256 / TX;
-    for (int id = 0; id < P->nblk; ++id) {
-        const DevBlock& h = P->hblk[id];
-        P->tile_first[id] = (int)P->htiles.size();
-        if (!P->hdom[h.domain].twod) {
-            for (int x = 0; x < h.nx; x += 256) P->htiles.push_back(Tile{id, x, 0, 1});
-            P->kind_mask |= 2;
-        } else {
-            for (int y = 0; y < h.ny; y += TY)
-                for (int x = 0; x < h.nx; x += TX) P->htiles.push_back(Tile{id, x, y, TX << 8});
-            P->kind_mask |= 1;
+    for (int l = 0; l <= P->maxlev; ++l) {
+        P->lev_first[l] = (int)P->htiles.size();
+        for (int id = 0; id < P->nblk; ++id) {
+            const DevBlock& h = P->hblk[id];
+            if (h.level != l) continue;
+            P->tile_first[id] = (int)P->htiles.size();
+            if (!P->hdom[h.domain].twod) {
+                for (int x = 0; x < h.nx; x += 256) P->htiles.push_back(Tile{id, x, 0, 1});
+                P->kind_mask |= 2;
+            } else {
+                for (int y = 0; y < h.ny; y += TY)
+                    for (int x = 0; x < h.nx; x += TX) P->htiles.push_back(Tile{id, x, y, TX << 8});
+                P->kind_mask |= 1;
+            }
+            P->tile_count[id] = (int)P->htiles.size() - P->tile_first[id];
         }
-        P->tile_count[id] = (int)P->htiles.size() - P->tile_first[id];
+        P->lev_count[l] = (int)P->htiles.size() - P->lev_first[l];
     }
     if (P->dtiles) hipFree(P->dtiles);
     P->dtiles = nullptr;
@@ -462,12 +476,100 @@ StageArgs base_args(janc_plan* P, const janc_time* tm, double* U, double* T, dou
     a.dt_log_cap = cap;
     a.tm = TimeArgs{tm->cfl, tm->dt_fixed, tm->t_end};
     a.status = P->ctx->dstatus;
-    (void)T;
+    if (P->flags & JANC_PLAN_CROSSOVER) {
+        a.cross = 1;
+        a.xlevels = P->maxlev + 1;
+        a.xred = P->dred;
+        a.Tbase = T;
+    }
     return a;
+}
+
+// Level l's slot triple in the crossover advance.
+Reduce level_red(const janc_plan* P, const StageArgs& base, int l) {
+    Reduce r = base.red;
+    if (base.cross) r.buf = P->dred + (size_t)l * 3 * P->red_stride;
+    return r;
+}
+
+// One crossover step (Fig. 2a, Alg. 2): two steps of level l + 1 before each step of
+// level l, deepest level first, dt_l = dt_0 / 2^l; then restriction and ring refill.
+hipError_t enqueue_crossover(janc_plan* P, const StageArgs& base, double* U, double* T,
+                             hipStream_t s) {
+    janc_ctx* c = P->ctx;
+    const int model = c->model, ns = c->ns;
+    double* Uin[3] = {U, P->U1, P->U2};
+    double* Uout[3] = {P->U1, P->U2, U};
+    double* Tin[3] = {T, P->T1, P->T2};
+    double* Tout[3] = {P->T1, P->T2, T};
+    std::vector<int> done(P->maxlev + 1, 0);
+    bool first = true;
+    hipError_t e = hipSuccess;
+    auto level_step = [&](int l) {
+        const int n = P->lev_count[l];
+        const bool last_of_level = done[l] == (1 << l) - 1;
+        ++done[l];
+        if (n == 0 || e != hipSuccess) return;
+        for (int st = 1; st <= 3 && e == hipSuccess; ++st) {
+            StageArgs a = base;
+            a.red = level_red(P, base, l);
+            a.stage = st;
+            a.Uin = Uin[st - 1];
+            a.Uout = Uout[st - 1];
+            a.Tin = Tin[st - 1];
+            a.Tout = Tout[st - 1];
+            a.reduce_out = (st == 3 && model == DETAILED) ? 0 : 1;
+            a.xfirst = (first && st == 1) ? 1 : 0;
+            a.xlast = (l == 0 && st == 3 && model != DETAILED) ? 1 : 0;
+            a.xskip_cov = last_of_level ? 1 : 0;
+            e = launch_stage(model, ns, P->kind_mask, P->tile_w, a, P->lev_first[l], n, s);
+            first = false;
+        }
+        if (e == hipSuccess && model == DETAILED) {
+            StageArgs a = base;
+            a.red = level_red(P, base, l);
+            a.stage = 3;
+            a.Uin = U;
+            a.Uout = U;
+            a.Tin = T;
+            a.Tout = T;
+            a.tiles = P->dtiles + P->lev_first[l];
+            a.ntiles = n;
+            a.xlast = (l == 0) ? 1 : 0;
+            a.xskip_cov = last_of_level ? 1 : 0;
+            e = launch_chem(model, ns, P->tile_w, a, s);
+        }
+    };
+    struct Rec {
+        decltype(level_step)& step;
+        int maxlev;
+        void run(int l) {
+            if (l < maxlev) {
+                run(l + 1);
+                run(l + 1);
+            }
+            step(l);
+        }
+    } rec{level_step, P->maxlev};
+    rec.run(0);
+    StageArgs a = base;
+    a.stage = 3;
+    a.Uin = U;
+    a.Uout = U;
+    a.Tin = T;
+    a.Tout = T;
+    for (int l = P->maxlev; l >= 1 && e == hipSuccess; --l) {
+        a.red = level_red(P, base, l - 1);   // restricted cells enter the coarse level's maxima
+        e = launch_restrict(model, ns, a, P->dfine + P->fine_off[l], (int)P->fine[l].size(), s);
+    }
+    if (e == hipSuccess && !P->ring_blocks.empty())
+        e = launch_ring_fill(model, ns, a, P->dring, (int)P->ring_blocks.size(), s);
+    return e;
 }
 
 // Enqueue one full step (3 stages, chemistry, restriction, ring refill).
 hipError_t enqueue_step(janc_plan* P, const StageArgs& base, double* U, double* T, hipStream_t s) {
+    if (base.cross) return enqueue_crossover(P, base, U, T, s);
     janc_ctx* c = P->ctx;
     const int model = c->model, ns = c->ns;
     double* Uin[3] = {U, P->U1, P->U2};
@@ -518,13 +620,24 @@ janc_status run_steps(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U,
                       int nsteps, double* t, double* dt_log, hipStream_t s) {
     HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
     const StageArgs base = base_args(P, tm, U, T, t, dt_log, nsteps);
-    HIPCHK(c, launch_clear_reduce(base.red, -1, s), "clear launch");
     HIPCHK(c, launch_zero_int(P->dstep, s), "counter launch");
     StageArgs a0 = base;
     a0.Uin = U;
     a0.Tin = T;
     a0.Tout = T;
-    HIPCHK(c, launch_init(c->model, c->ns, P->tile_w, a0, s), "init launch");
+    if (!base.cross) {
+        HIPCHK(c, launch_clear_reduce(base.red, -1, s), "clear launch");
+        HIPCHK(c, launch_init(c->model, c->ns, P->tile_w, a0, s), "init launch");
+    } else {
+        // one slot triple per level; each level's entry maxima into its buffer 0
+        for (int l = 0; l <= P->maxlev; ++l) {
+            a0.red = level_red(P, base, l);
+            HIPCHK(c, launch_clear_reduce(a0.red, -1, s), "clear launch");
+            a0.tiles = P->dtiles + P->lev_first[l];
+            a0.ntiles = P->lev_count[l];
+            HIPCHK(c, launch_init(c->model, c->ns, P->tile_w, a0, s), "init launch");
+        }
+    }
     if (nsteps == 0) return JANC_OK;
     if (P->flags & JANC_PLAN_NO_GRAPH) {
         for (int n = 0; n < nsteps; ++n) HIPCHK(c, enqueue_step(P, base, U, T, s), "step launch");
@@ -976,6 +1089,8 @@ janc_status janc_profile_step(janc_ctx* c, janc_plan* P, const janc_time* tm, do
                               double* T, double* t, double* ms, void* stream) {
     if (!c || !P || !tm || !U || !T || !t || !ms) return fail(c, JANC_EINVAL, "bad arguments");
     if (P->ctx != c) return fail(c, JANC_EINVAL, "plan belongs to another context");
+    if (P->flags & JANC_PLAN_CROSSOVER)
+        return fail(c, JANC_EINVAL, "per-kernel profiling times the synchronous advance");
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
     const StageArgs base = base_args(P, tm, U, T, t, nullptr, 0);

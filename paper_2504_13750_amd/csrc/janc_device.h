@@ -102,10 +102,12 @@ __device__ long long resolve(const StageArgs& a, CDom& D, int lev, int I, int J,
             const int li = I - B.i0, lj = J - B.j0;
             if (!ring_at(B, li, lj)) return B.offset + (long long)lj * B.nx + li;
         }
-        // level 0 tiles the domain and has no ring cells, so this ends
+        // level 0 tiles the domain and has no ring cells, so this ends; bit 2 of fl
+        // marks a source on a coarser level than the one asked for
         --lev;
         I >>= 1;
         J >>= 1;
+        fl |= 4u;
     }
 }
 
@@ -253,10 +255,18 @@ __device__ __forceinline__ double rk_combine(int stage, double u0, double us, do
     return (1.0 / 3.0) * u0 + (2.0 / 3.0) * (us + dt * L);
 }
 
+// dt of domain d for this step from the CFL slot of buffer `bin`; in the crossover
+// advance dt_0, from the largest bound over every level's slot triple.
 __device__ __forceinline__ double step_dt(const StageArgs& a, int d, int bin) {
     double dt;
     if (a.tm.dt_fixed > 0.0) {
         dt = a.tm.dt_fixed;
+    } else if (a.cross) {
+        double m = 0.0;
+        for (int l = 0; l < a.xlevels; ++l)
+            m = fmax(m, __longlong_as_double((long long)a.xred[((size_t)l * 3 + bin) * a.red.stride +
+                                                               2 * a.red.nunits + d]));
+        dt = a.tm.cfl / m;
     } else {
         dt = a.tm.cfl / slot_get(a.red, bin, 2 * a.red.nunits + d);
     }
@@ -285,11 +295,23 @@ __device__ __forceinline__ int xcd_chunk(int b, int n) {
     return x * q + min(x, r) + (b >> 3);
 }
 
+// CFL bound of a cell with wave speeds sx, sy at the spacing of its level (1/dx, 1/dy);
+// in the crossover advance at the spacing of level 0, so that dt_0 bounds every level.
+__device__ __forceinline__ double cfl_bound(const StageArgs& a, CDom& D, int lev, double sx,
+                                            double sy, double idx, double idy) {
+    if (a.cross) {
+        idx = ldexp(idx, -lev);
+        idy = ldexp(idy, -lev);
+    }
+    return sx * idx + (D.twod ? sy * idy : 0.0);
+}
+
 // Per-launch bookkeeping done by workgroup 0: rotate reduction buffers, dt and t.
 __device__ void stage_bookkeeping(const StageArgs& a, int owner_launch) {
     const int s = a.stage;
     const int bclear = (s + 1) % 3;
     for (int q = threadIdx.x; q < a.red.stride; q += WG) a.red.buf[(size_t)bclear * a.red.stride + q] = 0ull;
+    if (a.cross) owner_launch = a.xfirst;
     if (!owner_launch) return;
     if (s == 1) {
         const int step = *a.step;

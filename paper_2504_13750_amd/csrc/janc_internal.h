@@ -107,6 +107,14 @@ struct StageArgs {
     int dt_log_cap;
     TimeArgs tm;
     unsigned* status;
+    // crossover advance (per-level launches, dt_l = dt_0 / 2^l); all zero otherwise
+    int cross;
+    int xfirst;               // first launch of the step: computes dt_0
+    int xlast;                // last launch of the step: advances t and the step counter
+    int xskip_cov;            // last step of this level in the step: covered cells leave the maxima
+    int xlevels;              // levels with reduction slot triples
+    unsigned long long* xred; // all levels' slot triples (level l at l * 3 * red.stride)
+    const double* Tbase;      // T of the pool (coarser levels' current state)
 };
 
 // Launchers implemented in janc_kernels.hip.

@@ -79,7 +79,10 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
     const int lev = B.level;
     const int stage = a.stage;
     const int bin = stage - 1, bout = stage % 3;
-    const double dt = (stage == 1) ? step_dt(a, B.domain, 0) : a.dt[B.domain];
+    // crossover advance: dt_l = dt_0 / 2^l, dt_0 formed by the first launch of the step
+    const double dt = a.cross ? ldexp((a.xfirst && stage == 1) ? step_dt(a, B.domain, 0)
+                                                               : a.dt[B.domain], -lev)
+                              : (stage == 1) ? step_dt(a, B.domain, 0) : a.dt[B.domain];
     if (!(dt > 0.0)) return;   // finished domain: state unchanged
     const double dxl = D.dx0 / (double)(1 << lev), dyl = D.dy0 / (double)(1 << lev);
     const double idx = 1.0 / dxl, idy = 1.0 / dyl;
@@ -118,7 +121,9 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
                 else
                     src = resolve(a, D, lev, B.i0 + bi, B.j0 + bj, fl);
                 double T;
-                fetch<NU>(a, src, fl, a.Uin, a.Tin, ur[q], T);
+                // crossover: coarser levels are read at their current state
+                const bool base = a.cross && (fl & 4u);
+                fetch<NU>(a, src, fl, base ? a.U0 : a.Uin, base ? a.Tbase : a.Tin, ur[q], T);
                 halo_prims<M, NU>(ur[q], T, D, cmech(a.mech), vxr[q], vyr[q], pr[q]);
                 if (q == 0) Town = T;
             }
@@ -246,12 +251,12 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
         const unsigned st = owner_state<M, NU>(unew, Town, D, cmech(a.mech), T, c, vx, vy);
         a.Tout[oc] = T;
         if (st) atomicOr(a.status, st);
-        const bool skip = (stage == 3) && B.fine_child &&
+        const bool skip = (stage == 3) && B.fine_child && (!a.cross || a.xskip_cov) &&
                           covered_by_finer(a, D, lev, B.i0 + obi, B.j0 + obj);
         if (a.reduce_out && !st && !skip) {
             sx = fabs(vx) + c;
             sy = fabs(vy) + c;
-            sc = sx * idx + (D.twod ? sy * idy : 0.0);
+            sc = cfl_bound(a, D, lev, sx, sy, idx, idy);
         }
     }
     if (a.reduce_out)
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(WG, STAGE_WAVES) void stage_kernel(StageArgs a, int
     } else {
         if constexpr (HAS2D) stage_tile<M, NU, TX, TY>(a, tile, smem);
     }
-    if (a.stage == 3 && owner_launch && blockIdx.x == 0) {
+    if (a.stage == 3 && (a.cross ? a.xlast : owner_launch) && blockIdx.x == 0) {
         // t and the step counter are read by the next step's first stage only
         if (M != DETAILED) step_finish(a);
     }
@@ -334,7 +339,7 @@ __global__ __launch_bounds__(WG) void init_kernel(StageArgs a) {
         else {
             sx = fabs(vx) + c;
             sy = fabs(vy) + c;
-            sc = sx * idx + (D.twod ? sy * idy : 0.0);
+            sc = cfl_bound(a, D, lev, sx, sy, idx, idy);
         }
     }
     publish_max3(a.red, 0, 2 * slot, 2 * slot + 1, 2 * a.red.nunits + B.domain, sx, sy, sc, scratch);
@@ -475,9 +480,9 @@ __global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
     CMech* mech = cmech(a.mech);
     const CellRef r = tile_cell(a, tile, B);
     const int lev = B.level, slot = D.slot0 + lev;
-    const double dt = a.dt[B.domain];
+    const double dt = a.cross ? ldexp(a.dt[B.domain], -lev) : a.dt[B.domain];
     const double idx = (double)(1 << lev) / D.dx0, idy = (double)(1 << lev) / D.dy0;
-    if (blockIdx.x == 0) step_finish(a);
+    if (blockIdx.x == 0 && (!a.cross || a.xlast)) step_finish(a);
     if (!(dt > 0.0)) return;
     double sx = 0.0, sy = 0.0, sc = 0.0;
     unsigned st = 0u;
@@ -510,11 +515,12 @@ __global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
         st |= owner_state<DETAILED, NU>(u, T, D, mech, Tn, c, vx, vy);
         a.Tout[r.c] = Tn;
         if (st) atomicOr(a.status, st);
-        const bool skip = B.fine_child && covered_by_finer(a, D, lev, r.I, r.J);
+        const bool skip = B.fine_child && (!a.cross || a.xskip_cov) &&
+                          covered_by_finer(a, D, lev, r.I, r.J);
         if (!st && !skip) {
             sx = fabs(vx) + c;
             sy = fabs(vy) + c;
-            sc = sx * idx + (D.twod ? sy * idy : 0.0);
+            sc = cfl_bound(a, D, lev, sx, sy, idx, idy);
         }
     }
     publish_max3(a.red, 0, 2 * slot, 2 * slot + 1, 2 * a.red.nunits + B.domain, sx, sy, sc, scratch);
@@ -565,7 +571,7 @@ __global__ __launch_bounds__(WG) void restrict_kernel(StageArgs a, const int* fi
         else {
             sx = fmax(sx, fabs(vx) + c);
             sy = fmax(sy, fabs(vy) + c);
-            sc = fmax(sc, (fabs(vx) + c) * idx + (D.twod ? (fabs(vy) + c) * idy : 0.0));
+            sc = fmax(sc, cfl_bound(a, D, lev - 1, fabs(vx) + c, fabs(vy) + c, idx, idy));
         }
     }
     publish_max3(a.red, 0, 2 * cslot, 2 * cslot + 1, 2 * a.red.nunits + B.domain, sx, sy, sc,

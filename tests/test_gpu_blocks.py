@@ -1,5 +1,6 @@
 """GPU parity on block tables (AMR hierarchies and ensembles) against the oracle,
-and the invariances of the batched launch.
+in the synchronous and the crossover advance, and the invariances of the batched
+launch.
 
 Bar: max relative error per conserved field <= 1e-10 after N steps; the batched
 and per-block launch forms and block splits of a uniform grid are bitwise equal.
@@ -24,10 +25,12 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
 
-def _cmp_blocks(bcase, nsteps, tol=TOL, **kw):
+def _cmp_blocks(bcase, nsteps, tol=TOL, crossover=False, **kw):
+    if crossover:
+        kw["flags"] = kw.get("flags", 0) | janc.PLAN_CROSSOVER
     Ug, Tg, tg = run_blocks(bcase, nsteps, **kw)
     Uo, To = oracle.block_state(bcase)
-    Uo, To, to, _, _ = oracle.step_blocks(bcase, Uo, To, nsteps)
+    Uo, To, to, _, _ = oracle.step_blocks(bcase, Uo, To, nsteps, crossover=crossover)
     valid = np.zeros(bcase.pool_cells, bool)
     for b in bcase.blocks[bcase.blocks["valid"] != 0]:
         valid[b["offset"]:b["offset"] + b["nx"] * b["ny"]] = True
@@ -136,5 +139,39 @@ def test_bad_table_rejected():
     ctx = janc.Context(janc.ONESTEP)
     with pytest.raises(janc.JancError) as ei:
         ctx.plan(janc.domains_of(bc), bc.blocks, bc.pool_cells)
+    assert ei.value.code == -1
+    ctx.close()
+
+
+# ------------------------------------------------------------------ crossover advance
+def test_crossover_amr_onestep_vs_oracle():
+    _cmp_blocks(_small_amr(), 8, crossover=True)
+
+
+def test_crossover_amr_detailed_vs_oracle():
+    _cmp_blocks(_small_detailed_amr(), 2, crossover=True)
+
+
+def test_crossover_single_level_equals_synchronous_bitwise():
+    c = detonation_tube_case(nx=128, ny=32, seed=19)
+    bc, _ = _split_uniform(c, [0, 24, 64, 72, 128], [0, 8, 24, 32])
+    Ua, Ta, ta = run_blocks(bc, 20)
+    Ub, Tb, tb = run_blocks(bc, 20, flags=janc.PLAN_CROSSOVER)
+    assert np.array_equal(Ua, Ub) and np.array_equal(Ta, Tb) and np.array_equal(ta, tb)
+
+
+def test_crossover_graph_and_direct_launch_agree():
+    bc = _small_amr()
+    Ua, _, ta = run_blocks(bc, 3, flags=janc.PLAN_CROSSOVER)
+    Ub, _, tb = run_blocks(bc, 3, flags=janc.PLAN_CROSSOVER | janc.PLAN_NO_GRAPH)
+    assert np.array_equal(Ua, Ub) and np.array_equal(ta, tb)
+
+
+def test_crossover_per_block_rejected():
+    bc = _small_amr()
+    ctx = janc.Context(janc.ONESTEP)
+    with pytest.raises(janc.JancError) as ei:
+        ctx.plan(janc.domains_of(bc), bc.blocks, bc.pool_cells,
+                 janc.PLAN_CROSSOVER | janc.PLAN_PER_BLOCK)
     assert ei.value.code == -1
     ctx.close()
