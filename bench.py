@@ -64,15 +64,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-STAGE_SOURCES = ("janc_device.h", "janc_internal.h", "janc_kernels.hip")
+STAGE_SOURCES = ("csrc/janc_device.h", "csrc/janc_internal.h", "csrc/janc_kernels.hip",
+                 "build.py")
 
 
 def kernel_source_hash():
-    """sha256[:16] of the sources the stage kernel is compiled from."""
+    """sha256[:16] of the sources and build flags the stage kernel is compiled from."""
     import hashlib
     h = hashlib.sha256()
     for f in STAGE_SOURCES:
-        with open(os.path.join(ROOT, "paper_2504_13750_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(ROOT, "paper_2504_13750_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

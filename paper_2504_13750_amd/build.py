@@ -2,7 +2,10 @@
 
 Flags: -O3; FP64 everywhere; packed-FP32 instruction selection disabled
 (the library has no FP32 arithmetic on its hot path, and the packed forms are
-kept out deliberately).
+kept out deliberately); a*b+c is fused into an FMA only within one source
+expression (-ffp-contract=on), so that the rounding of a formula does not depend
+on how the compiler schedules a particular kernel instantiation: tile shapes and
+launch forms give bitwise-identical results.
 """
 
 import concurrent.futures as cf
@@ -15,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjanc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["janc_kernels.hip", "janc_adjoint.hip", "janc_api.hip"]
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-value", "-Wno-unused-result"]
 

@@ -23,6 +23,9 @@
 namespace janc {
 
 // ------------------------------------------------------------------ the stage tile
+#ifndef STAGE_SETS
+#define STAGE_SETS 1
+#endif
 // Points of a tile: the TX x TY owned positions first (point tid is thread tid's
 // own cell), then the x halo (3 columns each side of every row) and, for 2-D
 // tiles, the y halo (3 rows below and above every column).
@@ -38,8 +41,15 @@ struct Geom {
     static constexpr int NIX = (TX + 1) * TY;           // x interfaces
     static constexpr int NIY = TWO ? TX * (TY + 1) : 0; // y interfaces
     static constexpr int NEXT = 2 * TY + (TWO ? 2 * TX : 0);  // right column / top row, both sides
-    // LDS doubles: F+/F- and G+/G-, the four one-sided interface values, scratch
-    static constexpr int LDS = 2 * NXS + 2 * NYS + 2 * NIX + 2 * NIY + 16;
+    // LDS doubles of one set: F+/F- and G+/G-, the four one-sided interface values;
+    // NSET sets (two: the next component's fluxes are written while this one is
+    // reconstructed, one barrier per component), then scratch
+    static constexpr int SET = 2 * NXS + 2 * NYS + 2 * NIX + 2 * NIY;
+    static constexpr int NSET = STAGE_SETS;
+    static constexpr int LDS = NSET * SET + 16;
+    static constexpr int oFPX = 0, oFMX = NXS, oFPY = 2 * NXS, oFMY = 2 * NXS + NYS;
+    static constexpr int oHXP = 2 * NXS + 2 * NYS, oHXM = oHXP + NIX, oHYP = oHXM + NIX,
+                         oHYM = oHYP + NIY;
 
     // tile-local position (li, lj) of point p
     __device__ static void point(int p, int& li, int& lj) {
@@ -63,15 +73,9 @@ template <int M, int NU, int TX, int TY>
 __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
     using G = Geom<TX, TY>;
     static_assert(TX * TY == WG, "one owned cell per thread");
-    double* fpx = smem;
-    double* fmx = fpx + G::NXS;
-    double* fpy = fmx + G::NXS;
-    double* fmy = fpy + G::NYS;
-    double* hxp = fmy + G::NYS;      // WENO5 of F+ at x interfaces
-    double* hxm = hxp + G::NIX;      // WENO5 of F- at x interfaces
-    double* hyp = hxm + G::NIX;
-    double* hym = hyp + G::NIY;
-    double* scratch = hym + G::NIY;
+    // set k at smem + k * SET: F+ / F- of x (fpx, fmx) and y (fpy, fmy), the WENO5 of
+    // F+ and F- at x interfaces (hxp, hxm) and y interfaces (hyp, hym)
+    double* scratch = smem + G::NSET * G::SET;
 
     const int tid = threadIdx.x;
     const DevBlock B = a.blk[tile.block];
@@ -150,25 +154,23 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
     const int bxi = olj * G::PW + oli, byi = olj * TX + oli;
     const int rxi = olj * (TX + 1) + oli, ryi = olj * TX + oli;
     bool ext_ok = false;
-    int ext_str = 1;
-    const double* ext_base = fpx;
-    double* ext_out = hxp;
+    int ext_str = 1, ext_in = 0, ext_out = 0;   // offsets within a set
     if (tid < G::NEXT) {
         const int e = tid;
         if (e < 2 * TY) {          // x interface TX of row e % TY, F+ then F-
             const int side = e / TY, row = e - side * TY;
             ext_ok = row < th && tw == TX;
             const int r = row * (TX + 1) + TX, o = row * G::PW + TX;
-            ext_base = side ? fmx + o + 5 : fpx + o;
+            ext_in = side ? G::oFMX + o + 5 : G::oFPX + o;
             ext_str = side ? -1 : 1;
-            ext_out = (side ? hxm : hxp) + r;
+            ext_out = (side ? G::oHXM : G::oHXP) + r;
         } else {                   // y interface TY of column, F+ then F-
             const int h = e - 2 * TY, side = h / TX, col = h - side * TX;
             ext_ok = col < tw && th == TY;
             const int r = TY * TX + col, o = TY * TX + col;
-            ext_base = side ? fmy + o + 5 * TX : fpy + o;
+            ext_in = side ? G::oFMY + o + 5 * TX : G::oFPY + o;
             ext_str = side ? -TX : TX;
-            ext_out = (side ? hym : hyp) + r;
+            ext_out = (side ? G::oHYM : G::oHYP) + r;
         }
     }
 
@@ -180,10 +182,8 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
     double u0q[PF];
 #pragma unroll
     for (int k = 0; k < PF; ++k) u0q[k] = (ld0 && k < NU) ? a.U0[(size_t)k * a.pool + oc] : 0.0;
-#pragma unroll
-    for (int f = 0; f < NU; ++f) {
-        const double u0 = (stage == 1) ? ur[0][f] : u0q[f % PF];
-        if (f + PF < NU) u0q[f % PF] = ld0 ? a.U0[(size_t)(f + PF) * a.pool + oc] : 0.0;
+    // split fluxes of component f (Eq. 4.11) into set S
+    auto flux = [&](int f, double* S) {
 #pragma unroll
         for (int q = 0; q < G::NPT; ++q) {
             const double uf = ur[q][f];
@@ -191,47 +191,54 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
                 double F = uf * vxr[q];
                 if (f == 1) F += pr[q];
                 if (f == 3) F = (uf + pr[q]) * vxr[q];
-                fpx[xoff[q]] = 0.5 * (F + ax * uf);
-                fmx[xoff[q]] = 0.5 * (F - ax * uf);
+                S[G::oFPX + xoff[q]] = 0.5 * (F + ax * uf);
+                S[G::oFMX + xoff[q]] = 0.5 * (F - ax * uf);
             }
             if constexpr (G::TWO) {
                 if (needy[q]) {
                     double Gf = uf * vyr[q];
                     if (f == 2) Gf += pr[q];
                     if (f == 3) Gf = (uf + pr[q]) * vyr[q];
-                    fpy[yoff[q]] = 0.5 * (Gf + ay * uf);
-                    fmy[yoff[q]] = 0.5 * (Gf - ay * uf);
+                    S[G::oFPY + yoff[q]] = 0.5 * (Gf + ay * uf);
+                    S[G::oFMY + yoff[q]] = 0.5 * (Gf - ay * uf);
                 }
             }
         }
-        __syncthreads();
-        // one-sided WENO5 reconstructions: each thread takes the left x interface
-        // and the lower y interface of its own position (both sides, fixed LDS
-        // offsets); the right column and top row of interfaces are the extra tasks
-        // of the first threads. F- reads its stencil mirrored.
+    };
+    // one-sided WENO5 reconstructions from set S into set S: each thread takes the
+    // left x interface and the lower y interface of its own position (both sides,
+    // fixed LDS offsets); the right column and top row of interfaces are the extra
+    // tasks of the first threads. F- reads its stencil mirrored.
+    auto recon = [&](double* S) {
         if (vxi) {
-            const double* P = fpx + bxi;
-            const double* Mn = fmx + bxi;
-            hxp[rxi] = weno5(P[0], P[1], P[2], P[3], P[4]);
-            hxm[rxi] = weno5(Mn[5], Mn[4], Mn[3], Mn[2], Mn[1]);
+            const double* P = S + G::oFPX + bxi;
+            const double* Mn = S + G::oFMX + bxi;
+            S[G::oHXP + rxi] = weno5(P[0], P[1], P[2], P[3], P[4]);
+            S[G::oHXM + rxi] = weno5(Mn[5], Mn[4], Mn[3], Mn[2], Mn[1]);
         }
         if constexpr (G::TWO) {
             if (vyi) {
-                const double* P = fpy + byi;
-                const double* Mn = fmy + byi;
-                hyp[ryi] = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX]);
-                hym[ryi] = weno5(Mn[5 * TX], Mn[4 * TX], Mn[3 * TX], Mn[2 * TX], Mn[TX]);
+                const double* P = S + G::oFPY + byi;
+                const double* Mn = S + G::oFMY + byi;
+                S[G::oHYP + ryi] = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX]);
+                S[G::oHYM + ryi] = weno5(Mn[5 * TX], Mn[4 * TX], Mn[3 * TX], Mn[2 * TX], Mn[TX]);
             }
         }
         if (ext_ok) {
-            const double* b = ext_base;
-            *ext_out = weno5(b[0], b[ext_str], b[2 * ext_str], b[3 * ext_str], b[4 * ext_str]);
+            const double* b = S + ext_in;
+            S[ext_out] = weno5(b[0], b[ext_str], b[2 * ext_str], b[3 * ext_str], b[4 * ext_str]);
         }
-        __syncthreads();
+    };
+    // flux difference (Eq. 4.10), source and RK stage of component f from set S
+    auto update = [&](int f, const double* S, double u0) {
         if (own) {
+            const double* hxp = S + G::oHXP;
+            const double* hxm = S + G::oHXM;
             const int rx = olj * (TX + 1) + oli;
             double L = -((hxp[rx + 1] + hxm[rx + 1]) - (hxp[rx] + hxm[rx])) * idx;
             if constexpr (G::TWO) {
+                const double* hyp = S + G::oHYP;
+                const double* hym = S + G::oHYM;
                 const int ry = olj * TX + oli;
                 L -= ((hyp[ry + TX] + hym[ry + TX]) - (hyp[ry] + hym[ry])) * idy;
             }
@@ -241,6 +248,28 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
             const double un = rk_combine(stage, u0, ur[0][f], L, dt);
             a.Uout[(size_t)f * a.pool + oc] = un;
             unew[f] = un;
+        }
+    };
+    if constexpr (G::NSET == 2) {
+        flux(0, smem);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int f = 0; f < NU; ++f) {
+        const double u0 = (stage == 1) ? ur[0][f] : u0q[f % PF];
+        if (f + PF < NU) u0q[f % PF] = ld0 ? a.U0[(size_t)(f + PF) * a.pool + oc] : 0.0;
+        double* S = smem + (G::NSET == 2 ? (f & 1) * G::SET : 0);
+        if constexpr (G::NSET == 2) {
+            recon(S);
+            if (f + 1 < NU) flux(f + 1, smem + ((f + 1) & 1) * G::SET);
+            __syncthreads();
+            update(f, S, u0);
+        } else {
+            flux(f, S);
+            __syncthreads();
+            recon(S);
+            __syncthreads();
+            update(f, S, u0);
         }
     }
 
