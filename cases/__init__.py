@@ -20,7 +20,7 @@ from .common import (BC_PERIODIC, BC_ZEROGRAD, BC_SLIPWALL, BC_DIRICHLET,
 from .sod import sod_case
 from .detonation import (cj_state, znd_rate_constant, znd_profile,
                          detonation_tube_case, adjoint_case, ensemble_case)
-from .mechanism import synthetic_mechanism, Mechanism
+from .mechanism import synthetic_mechanism, two_range_mechanism, Mechanism
 from .amr import amr_case
 
 __all__ = [
@@ -29,5 +29,5 @@ __all__ = [
     "Case", "BlockCase", "Domain",
     "sod_case", "cj_state", "znd_rate_constant", "znd_profile",
     "detonation_tube_case", "adjoint_case", "ensemble_case",
-    "synthetic_mechanism", "Mechanism", "amr_case",
+    "synthetic_mechanism", "two_range_mechanism", "Mechanism", "amr_case",
 ]

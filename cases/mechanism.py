@@ -18,7 +18,7 @@ a6 = 3 * (1 + U[-0.05, 0.05]). SI conversion: A * 1e-6^(order-1), Ea * 4184.
 
 import itertools
 from dataclasses import dataclass
-from typing import List
+from typing import List, Optional
 
 import numpy as np
 
@@ -47,6 +47,8 @@ class Mechanism:
     reversible: np.ndarray    # [nr] int
     A_cgs: np.ndarray
     Ea_kcal: np.ndarray
+    nasa_high: Optional[np.ndarray] = None   # [ns, 7] high-temperature set (two-range NASA-7)
+    t_mid: Optional[np.ndarray] = None       # [ns] K: the high set applies for T >= t_mid
 
     @property
     def ns(self) -> int:
@@ -125,3 +127,26 @@ def fresh_mass_fractions(mech: Mechanism) -> np.ndarray:
     Y[mech.species.index("B2")] = 0.23
     Y[mech.species.index("C2")] = 0.74
     return Y
+
+
+def two_range_mechanism(mech: Mechanism, t_mid: float = 1800.0, eps: float = 0.05,
+                        seed: int = 13752) -> Mechanism:
+    """The same mechanism with two-range NASA-7 thermodynamics: below t_mid the
+    original coefficients, above it a second set whose cp/R differs by
+    eps_k (T - t_mid)^2 / t_mid^2 (eps_k ~ eps U[0.5, 1]) and whose a5, a6 keep h and s
+    continuous at t_mid, so cp, dcp/dT, h and s are all continuous there."""
+    rng = np.random.default_rng(seed)
+    low = np.array(mech.nasa, dtype=float)
+    high = low.copy()
+    e = eps * rng.uniform(0.5, 1.0, size=mech.ns)
+    Tm = float(t_mid)
+    d0, d1, d2 = e, -2.0 * e / Tm, e / Tm ** 2        # added to a0, a1, a2
+    high[:, 0] += d0
+    high[:, 1] += d1
+    high[:, 2] += d2
+    high[:, 5] -= Tm * (d0 + d1 * Tm / 2.0 + d2 * Tm ** 2 / 3.0)      # h continuous
+    high[:, 6] -= d0 * np.log(Tm) + d1 * Tm + d2 * Tm ** 2 / 2.0       # s continuous
+    out = Mechanism(**{k: getattr(mech, k) for k in mech.__dataclass_fields__})
+    out.nasa_high = high
+    out.t_mid = np.full(mech.ns, Tm)
+    return out

@@ -58,8 +58,8 @@ enum {
 enum { JANC_MAX_FIELDS = 16, JANC_MAX_LEVELS = 8, JANC_MAX_PROBES = 8 };
 
 /* Detailed mechanism (host arrays, copied at janc_create), SI units:
- * M [ns] kg/mol; nasa [ns][7] single-range NASA-7 coefficients a0..a6
- * (Eq. 4.3-4.5); A [nr] in (m^3/mol)^(order-1)/s; b [nr]; Ea [nr] J/mol
+ * M [ns] kg/mol; nasa [ns][7] NASA-7 coefficients a0..a6 (Eq. 4.3-4.5): the
+ * only set, or with nasa_high / t_mid the low-temperature set (T < t_mid); A [nr] in (m^3/mol)^(order-1)/s; b [nr]; Ea [nr] J/mol
  * (Eq. 4.8); nu_f, nu_b [nr][ns] integer stoichiometry (Eq. 4.6); tb [nr][ns]
  * third-body efficiencies, used when has_tb[i] (Eq. 4.7); reversible [nr]:
  * k_b = k_f / K_eq (Eq. 4.9) when set, else 0. The last species is the
@@ -70,6 +70,9 @@ typedef struct {
     const int *nu_f, *nu_b;
     const double *tb;
     const int *has_tb, *reversible;
+    const double *nasa_high;   /* [ns][7] high-temperature NASA-7 set, or NULL (one range) */
+    const double *t_mid;       /* [ns] K: nasa_high applies for T >= t_mid (one value for all
+                                  species, else JANC_EINVAL); NULL with nasa_high */
 } janc_mech;
 
 /* Per-problem physics: gamma and R for CPG/ONESTEP (R only scales T = p/(rho R));

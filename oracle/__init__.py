@@ -25,7 +25,8 @@ PI = C.POINTER(C.c_int)
 
 class OMech(C.Structure):
     _fields_ = [("ns", I), ("nr", I), ("M", PD), ("nasa", PD), ("A", PD), ("b", PD), ("Ea", PD),
-                ("nuf", PI), ("nub", PI), ("tb", PD), ("has_tb", PI), ("rev", PI)]
+                ("nuf", PI), ("nub", PI), ("tb", PD), ("has_tb", PI), ("rev", PI),
+                ("nasa_high", PD), ("t_mid", PD)]
 
 
 class OPhys(C.Structure):
@@ -101,8 +102,13 @@ class _MechView:
         b = k(mech.b, _f64); Ea = k(mech.Ea, _f64); nuf = k(mech.nu_f, _i32)
         nub = k(mech.nu_b, _i32); tb = k(mech.tb, _f64); htb = k(mech.has_tb, _i32)
         rev = k(mech.reversible, _i32)
+        hi = tm = None
+        if getattr(mech, "nasa_high", None) is not None:
+            hi = k(mech.nasa_high, _f64)
+            tm = k(mech.t_mid, _f64)
         self.s = OMech(len(mech.M), len(mech.A), _p(M), _p(nasa), _p(A), _p(b), _p(Ea),
-                       _p(nuf, PI), _p(nub, PI), _p(tb), _p(htb, PI), _p(rev, PI))
+                       _p(nuf, PI), _p(nub, PI), _p(tb), _p(htb, PI), _p(rev, PI),
+                       None if hi is None else _p(hi), None if tm is None else _p(tm))
         self.ptr = C.byref(self.s)
 
 

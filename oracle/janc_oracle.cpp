@@ -15,7 +15,7 @@
  *
  * What is computed (paper Sec. 4):
  *   conserved U = [rho, rho u, rho v, E, rho Y_1 .. rho Y_{Ns-1}]     (Eq. 4.1)
- *   thermally perfect mixture, NASA-7 polynomials                    (Eq. 4.2-4.5)
+ *   thermally perfect mixture, NASA-7 polynomials (one or two ranges) (Eq. 4.2-4.5)
  *   T from the internal energy by Newton, warm-started               (Sec. 4.2, last paragraph)
  *   Lax-Friedrichs flux vector splitting with a global alpha         (Eq. 4.11)
  *   WENO5 reconstruction of F+ and F-, 3 ghost layers                (Sec. 4.2)
@@ -96,6 +96,7 @@ template <class S> inline bool finite(const S& x) { return std::isfinite(val(x))
 struct MechData {
     int ns = 0, nr = 0;
     std::vector<double> M, nasa, A, b, Ea, tb;
+    std::vector<double> nasa_hi, tmid;   // two-range NASA-7: high set, switch temperature
     std::vector<int> nuf, nub, has_tb, rev;
 };
 
@@ -121,6 +122,14 @@ template <class S> S nasa_s(const double* a, const S& T) {
            a[4] * T * T * T * T / 4.0 + a[6];
 }
 
+// NASA-7 coefficients of species k at T. With two temperature ranges (as NASA-7
+// tables are published) the high set applies for T >= t_mid of the species, the low
+// set below; with one range the single set.
+template <class S> const double* coeffs(const MechData& m, int k, const S& T) {
+    if (!m.nasa_hi.empty() && val(T) >= m.tmid[k]) return &m.nasa_hi[7 * k];
+    return &m.nasa[7 * k];
+}
+
 // Mass fractions of all Ns species from the conserved vector (last = complement).
 template <class S> void mass_fractions(const MechData& m, const S* U, const S& rho, S* Y) {
     S sum = 0.0;
@@ -137,7 +146,7 @@ template <class S> void mixture_e_cv(const MechData& m, const S* Y, const S& T, 
     cv = 0.0;
     for (int k = 0; k < m.ns; ++k) {
         double Rk = RU / m.M[k];
-        const double* a = &m.nasa[7 * k];
+        const double* a = coeffs(m, k, T);
         e = e + Y[k] * Rk * (nasa_h(a, T) - T);
         cv = cv + Y[k] * Rk * (nasa_cp(a, T) - 1.0);
     }
@@ -279,8 +288,8 @@ void production(const MechData& m, const S& rho, const S& T, const S* rhoY, S* w
     X[nt] = (rho - sum) / m.M[nt];
     S htil[32], stil[32];
     for (int j = 0; j < ns; ++j) {
-        htil[j] = nasa_h(&m.nasa[7 * j], T);
-        stil[j] = nasa_s(&m.nasa[7 * j], T);
+        htil[j] = nasa_h(coeffs(m, j, T), T);
+        stil[j] = nasa_s(coeffs(m, j, T), T);
     }
     for (int k = 0; k < ns; ++k) wdot[k] = 0.0;
     if (J) for (int q = 0; q < nt * nt; ++q) J[q] = 0.0;
@@ -1325,6 +1334,7 @@ struct OMech {
     const int *nuf, *nub;
     const double* tb;
     const int *has_tb, *rev;
+    const double *nasa_high, *t_mid;   // two-range NASA-7 (both null: one range)
 };
 struct OPhys { int model; double gamma, R, Q, Ea, k; };
 struct OGrid { int nx, ny; double dx, dy; int bc[4]; };
@@ -1336,6 +1346,10 @@ MechData mech_from(const OMech* m) {
     d.ns = m->ns; d.nr = m->nr;
     d.M.assign(m->M, m->M + m->ns);
     d.nasa.assign(m->nasa, m->nasa + 7 * m->ns);
+    if (m->nasa_high && m->t_mid) {
+        d.nasa_hi.assign(m->nasa_high, m->nasa_high + 7 * m->ns);
+        d.tmid.assign(m->t_mid, m->t_mid + m->ns);
+    }
     d.A.assign(m->A, m->A + m->nr);
     d.b.assign(m->b, m->b + m->nr);
     d.Ea.assign(m->Ea, m->Ea + m->nr);
@@ -1470,7 +1484,8 @@ int oracle_primitives(const OPhys* p, const OMech* m, long long n, const double*
 double oracle_weno5(const double* f) { return weno5(f[0], f[1], f[2], f[3], f[4]); }
 
 void oracle_species_thermo(const OMech* m, int k, double T, double* h, double* cp, double* s) {
-    const double* a = &m->nasa[7 * k];
+    const double* a = (m->nasa_high && m->t_mid && T >= m->t_mid[k]) ? &m->nasa_high[7 * k]
+                                                                      : &m->nasa[7 * k];
     double Rk = RU / m->M[k];
     *h = Rk * nasa_h(a, T);
     *cp = Rk * nasa_cp(a, T);

@@ -118,11 +118,16 @@ class _Mech:
         self.keep = [f64(mech.M), f64(mech.nasa), f64(mech.A), f64(mech.b), f64(mech.Ea),
                      i32(mech.nu_f), i32(mech.nu_b), f64(mech.tb), i32(mech.has_tb),
                      i32(mech.reversible)]
+        hi = getattr(mech, "nasa_high", None)
+        if hi is not None:
+            self.keep += [f64(hi), f64(mech.t_mid)]
         k = self.keep
         pd = lambda a: a.ctypes.data_as(L.PD)
         pi = lambda a: a.ctypes.data_as(L.PI)
         self.s = L.janc_mech(len(mech.M), len(mech.A), pd(k[0]), pd(k[1]), pd(k[2]), pd(k[3]),
-                             pd(k[4]), pi(k[5]), pi(k[6]), pd(k[7]), pi(k[8]), pi(k[9]))
+                             pd(k[4]), pi(k[5]), pi(k[6]), pd(k[7]), pi(k[8]), pi(k[9]),
+                             pd(k[10]) if hi is not None else None,
+                             pd(k[11]) if hi is not None else None)
 
 
 # ------------------------------------------------------------------ context

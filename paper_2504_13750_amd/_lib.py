@@ -17,7 +17,8 @@ VP = C.c_void_p
 
 class janc_mech(C.Structure):
     _fields_ = [("ns", I), ("nr", I), ("M", PD), ("nasa", PD), ("A", PD), ("b", PD), ("Ea", PD),
-                ("nu_f", PI), ("nu_b", PI), ("tb", PD), ("has_tb", PI), ("reversible", PI)]
+                ("nu_f", PI), ("nu_b", PI), ("tb", PD), ("has_tb", PI), ("reversible", PI),
+                ("nasa_high", PD), ("t_mid", PD)]
 
 
 class janc_physics(C.Structure):

@@ -156,6 +156,18 @@ janc_status build_mech(janc_ctx* c, const janc_mech* m) {
         d.Rk[k] = RU / m->M[k];
         for (int q = 0; q < 7; ++q) d.nasa[k][q] = m->nasa[7 * k + q];
     }
+    if ((m->nasa_high == nullptr) != (m->t_mid == nullptr))
+        return fail(c, JANC_EINVAL, "nasa_high and t_mid go together");
+    if (m->nasa_high) {
+        d.two_range = 1;
+        for (int k = 0; k < m->ns; ++k) {
+            if (!(m->t_mid[k] > 0.0)) return fail(c, JANC_EINVAL, "t_mid of species %d not positive", k);
+            if (m->t_mid[k] != m->t_mid[0])
+                return fail(c, JANC_EINVAL, "t_mid must be the same for every species");
+            d.tmid[k] = m->t_mid[k];
+            for (int q = 0; q < 7; ++q) d.nasa_hi[k][q] = m->nasa_high[7 * k + q];
+        }
+    }
     for (int i = 0; i < m->nr; ++i) {
         d.lnA[i] = (m->A[i] > 0.0) ? std::log(m->A[i]) : -INFINITY;
         d.b[i] = m->b[i];

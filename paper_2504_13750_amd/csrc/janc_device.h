@@ -154,11 +154,16 @@ __device__ __forceinline__ void halo_prims(const double (&u)[NU], double T, cons
 }
 
 // Newton for T from the internal energy on mixture NASA coefficients
-// (Y fixed during the solve, so the species sums are formed once).
+// (Y fixed during the solve, so the species sums are formed once). With two
+// NASA-7 ranges (one t_mid for all species) both mixture sets are formed and
+// each iteration uses the set of the current T.
 template <int NS>
 __device__ __forceinline__ unsigned newton_T(const double (&Y)[NS], double e, CMech* m,
                                              double& T, double& cv, double& Rmix) {
     double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0, b4 = 0.0, b5 = 0.0;
+    double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0, h4 = 0.0, h5 = 0.0;
+    const bool two = m->two_range != 0;
+    const double tm = m->tmid[0];
     Rmix = 0.0;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
@@ -170,13 +175,29 @@ __device__ __forceinline__ unsigned newton_T(const double (&Y)[NS], double e, CM
         b3 += w * m->nasa[k][3];
         b4 += w * m->nasa[k][4];
         b5 += w * m->nasa[k][5];
+        if (two) {
+            h0 += w * m->nasa_hi[k][0];
+            h1 += w * m->nasa_hi[k][1];
+            h2 += w * m->nasa_hi[k][2];
+            h3 += w * m->nasa_hi[k][3];
+            h4 += w * m->nasa_hi[k][4];
+            h5 += w * m->nasa_hi[k][5];
+        }
     }
-    const double c0 = b0 - Rmix, c1 = 0.5 * b1, c2 = b2 * (1.0 / 3.0), c3 = 0.25 * b3,
-                 c4 = 0.2 * b4;
+    // e(T) and cv(T) of the mixture at T
+    auto eval = [&](double Tc, double& ec, double& cvv) {
+        const bool hi = two && Tc >= tm;
+        const double B0 = hi ? h0 : b0, B1 = hi ? h1 : b1, B2 = hi ? h2 : b2, B3 = hi ? h3 : b3,
+                     B4 = hi ? h4 : b4, B5 = hi ? h5 : b5;
+        const double c0 = B0 - Rmix, c1 = 0.5 * B1, c2 = B2 * (1.0 / 3.0), c3 = 0.25 * B3,
+                     c4 = 0.2 * B4;
+        ec = Tc * (c0 + Tc * (c1 + Tc * (c2 + Tc * (c3 + Tc * c4)))) + B5;
+        cvv = c0 + Tc * (B1 + Tc * (B2 + Tc * (B3 + Tc * B4)));
+    };
     unsigned st = STB_NEWTON;
     for (int it = 0; it < 50; ++it) {
-        const double ec = T * (c0 + T * (c1 + T * (c2 + T * (c3 + T * c4)))) + b5;
-        const double cvv = c0 + T * (b1 + T * (b2 + T * (b3 + T * b4)));
+        double ec, cvv;
+        eval(T, ec, cvv);
         const double dT = (ec - e) / cvv;
         T -= dT;
         if (!(fabs(dT) <= 1e-12 * fabs(T))) {
@@ -186,7 +207,8 @@ __device__ __forceinline__ unsigned newton_T(const double (&Y)[NS], double e, CM
         st = 0u;
         break;
     }
-    cv = c0 + T * (b1 + T * (b2 + T * (b3 + T * b4)));
+    double ec;
+    eval(T, ec, cv);
     return st;
 }
 

@@ -54,10 +54,13 @@ struct Tile {
 // Detailed mechanism in the layout the kernels read (uniform loads).
 struct DevMech {
     int ns, nr;
-    int pad[2];
+    int two_range;                     // a high-temperature NASA-7 set is present
+    int pad;
     double invM[MAXS];
     double Rk[MAXS];                   // R_u / M_k
-    double nasa[MAXS][7];
+    double nasa[MAXS][7];              // the one set, or the low-temperature set
+    double nasa_hi[MAXS][7];           // high-temperature set (T >= tmid)
+    double tmid[MAXS];
     double lnA[MAXR], b[MAXR], EaR[MAXR];
     int rev[MAXR], has_tb[MAXR], dnsum[MAXR], pad2[MAXR];
     int lf[MAXR][4], lb[MAXR][4];      // reactant / product species lists, padded with ns (= 1.0)

@@ -399,10 +399,13 @@ __device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, dou
     const double lnC = log(PATM / RU) - lnT;      // ln(p_atm / (R_u T))
 #pragma unroll
     for (int j = 0; j < NS; ++j) {                 // h/(R T) - s/R per species
-        gts[j * WG + tid] = m->nasa[j][0] * (1.0 - lnT) -
-                T * (0.5 * m->nasa[j][1] + T * (m->nasa[j][2] * (1.0 / 6.0) +
-                T * (m->nasa[j][3] * (1.0 / 12.0) + T * (m->nasa[j][4] * 0.05)))) +
-                m->nasa[j][5] * invT - m->nasa[j][6];
+        const bool hi = m->two_range && T >= m->tmid[j];
+        double a[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) a[q] = hi ? m->nasa_hi[j][q] : m->nasa[j][q];
+        gts[j * WG + tid] = a[0] * (1.0 - lnT) -
+                T * (0.5 * a[1] + T * (a[2] * (1.0 / 6.0) + T * (a[3] * (1.0 / 12.0) + T * (a[4] * 0.05)))) +
+                a[5] * invT - a[6];
     }
     double J[NT][NT];
 #pragma unroll
@@ -658,7 +661,7 @@ __global__ void prim_to_cons_kernel(const DevMech* mech, double gamma, double R,
         double Rm = 0.0, e = 0.0;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            const double* a = mech->nasa[k];
+            const double* a = (mech->two_range && Tt >= mech->tmid[k]) ? mech->nasa_hi[k] : mech->nasa[k];
             const double h = Tt * (a[0] + Tt * (0.5 * a[1] + Tt * (a[2] * (1.0 / 3.0) +
                              Tt * (0.25 * a[3] + Tt * (0.2 * a[4]))))) + a[5];
             Rm += Y[k] * mech->Rk[k];

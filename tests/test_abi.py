@@ -37,7 +37,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.janc_physics) == 40
     assert ctypes.sizeof(L.janc_time) == 24
     assert ctypes.sizeof(L.janc_grid) == 8 + 16 + 16 + 4 * 16 * 8
-    assert ctypes.sizeof(L.janc_mech) == 8 + 10 * 8
+    assert ctypes.sizeof(L.janc_mech) == 8 + 12 * 8
 
 
 def test_block_dtype_matches_cases():

@@ -120,6 +120,25 @@ def test_detailed_front_uniform():
     _compare(c, 4)
 
 
+def test_detailed_front_two_range_thermo():
+    """The same front with two-range NASA-7 data switching at 1800 K, inside the front's
+    1200-2500 K span, so Newton, the Gibbs terms and the initial energy use both sets."""
+    from cases import synthetic_mechanism, two_range_mechanism
+    c = detailed_front_case(nx=48, ny=40, mech=two_range_mechanism(synthetic_mechanism()))
+    _compare(c, 4)
+
+
+def test_species_dependent_t_mid_rejected():
+    import copy
+    import paper_2504_13750_amd as janc
+    from cases import synthetic_mechanism, two_range_mechanism
+    m = copy.deepcopy(two_range_mechanism(synthetic_mechanism()))
+    m.t_mid[2] = 1500.0
+    with pytest.raises(janc.JancError) as ei:
+        janc.Context(janc.DETAILED, m)
+    assert ei.value.code == -1
+
+
 def test_zero_steps_only_resolves_temperature():
     c = detailed_front_case(nx=32, ny=16)
     Ug, Tg, tg, _ = run_uniform(c, 0)
