@@ -93,9 +93,23 @@ typedef struct {
 
 /* Time step: dt = cfl / max((|u|+c)/dx + (|v|+c)/dy) over solved cells, or
  * dt_fixed when > 0; clipped so that t does not pass t_end when t_end > 0
- * (steps after t_end leave the state unchanged). */
+ * (steps after t_end leave the state unchanged). dt is formed from the state at
+ * the start of the step.
+ *
+ * split selects how the chemistry (JANC_MODEL_DETAILED only) is combined with
+ * the flux update (Sec. 4.2):
+ *   JANC_SPLIT_LIE    three RK stages over dt, then the point-implicit step over
+ *                     dt (the order of the paper's advance_one_step listing);
+ *   JANC_SPLIT_STRANG point-implicit step over dt/2, three RK stages over dt,
+ *                     point-implicit step over dt/2 (Strang splitting, Sec. 4.2).
+ * Any other value, and JANC_SPLIT_STRANG with a model without chemistry, is
+ * JANC_EINVAL. */
+enum { JANC_SPLIT_LIE = 0, JANC_SPLIT_STRANG = 1 };
+
 typedef struct {
     double cfl, dt_fixed, t_end;
+    int split;
+    int pad_;
 } janc_time;
 
 typedef struct janc_ctx janc_ctx;
@@ -197,7 +211,8 @@ janc_status janc_step_blocks(janc_ctx *ctx, janc_plan *plan, const janc_time *ti
  * `stream` around each launch group. ms (host) [6] receives the durations in
  * milliseconds of RK stage 1, stage 2, stage 3, the chemistry step, the
  * restriction (all levels) and the ring refill. U_pool, T_pool and t advance by
- * the step. Synchronizes the stream. Crossover plans return JANC_EINVAL. */
+ * the step. Synchronizes the stream. Crossover plans and Strang splitting return
+ * JANC_EINVAL. */
 janc_status janc_profile_step(janc_ctx *ctx, janc_plan *plan, const janc_time *time,
                               double *U_pool, double *T_pool, double *t, double *ms,
                               void *stream);

@@ -38,7 +38,7 @@ class OGrid(C.Structure):
 
 
 class OTime(C.Structure):
-    _fields_ = [("cfl", D), ("dt_fixed", D), ("t_end", D)]
+    _fields_ = [("cfl", D), ("dt_fixed", D), ("t_end", D), ("split", I), ("pad", I)]
 
 
 class ODomain(C.Structure):
@@ -177,15 +177,19 @@ def rhs(case, U, T):
     return L
 
 
-def step(case, U, T, nsteps, t=0.0, cfl=None, dt_fixed=None, t_end=None, check=True):
-    """Advance nsteps; returns (U, T, t, dt_log, status)."""
+def step(case, U, T, nsteps, t=0.0, cfl=None, dt_fixed=None, t_end=None, check=True,
+         strang=False):
+    """Advance nsteps; returns (U, T, t, dt_log, status).
+
+    strang=False: chemistry over dt after the RK stages (Lie); True: over dt/2 before
+    and after them (Strang splitting, Sec. 4.2)."""
     U = _f64(U).copy()
     T = _f64(T).copy()
     mv = _MechView(case.mech)
     ph, g = _phys(case), _grid(case)
     tm = OTime(case.cfl if cfl is None else cfl,
                case.dt_fixed if dt_fixed is None else dt_fixed,
-               case.t_end if t_end is None else t_end)
+               case.t_end if t_end is None else t_end, 1 if strang else 0, 0)
     bp = _bc_prim(case.nU, case.bc, case.bc_prim)
     tt = D(t)
     dts = np.zeros(max(nsteps, 1))
@@ -236,11 +240,11 @@ def block_state(bcase):
 
 
 def step_blocks(bcase, U, T, nsteps, t=None, cfl=None, dt_fixed=None, t_end=None, check=True,
-                crossover=False):
+                crossover=False, strang=False):
     """Advance a block table nsteps; returns (U, T, t[ndom], dt_log[nsteps, ndom], status).
 
     crossover=False: synchronous advance (paper Fig. 2b); True: crossover advance (Fig. 2a,
-    Alg. 2), where a step is one level-0 step (dt_log holds dt_0)."""
+    Alg. 2), where a step is one level-0 step (dt_log holds dt_0). strang as in step()."""
     U = _f64(U).copy()
     T = _f64(T).copy()
     nd = len(bcase.domains)
@@ -253,7 +257,7 @@ def step_blocks(bcase, U, T, nsteps, t=None, cfl=None, dt_fixed=None, t_end=None
     blocks = np.ascontiguousarray(bcase.blocks)
     tm = OTime(bcase.cfl if cfl is None else cfl,
                bcase.dt_fixed if dt_fixed is None else dt_fixed,
-               bcase.t_end if t_end is None else t_end)
+               bcase.t_end if t_end is None else t_end, 1 if strang else 0, 0)
     tt = np.zeros(nd) if t is None else _f64(t).copy()
     dts = np.zeros((max(nsteps, 1), nd))
     st = lib().oracle_step_blocks(I(bcase.model), mv.ptr, I(nd), doms, _p(bp), I(len(blocks)),

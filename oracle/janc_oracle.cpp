@@ -637,7 +637,9 @@ int rhs_uniform(const GridCfg& g, const Phys<S>& ph, const S* U, const S* T, con
     return rhs_ext(ph, E, ax, ay, g.dx, g.dy, L);
 }
 
-struct TimeCfg { double cfl, dt_fixed, t_end; };
+// split = 0: chemistry over dt after the RK stages (Lie, the order of the paper's
+// advance_one_step listing); 1: over dt/2 before and after them (Strang, Sec. 4.2).
+struct TimeCfg { double cfl, dt_fixed, t_end; int split; };
 
 template <class S>
 int choose_dt(const TimeCfg& tc, const S& cflmax, double t, S& dt) {
@@ -651,7 +653,23 @@ int choose_dt(const TimeCfg& tc, const S& cflmax, double t, S& dt) {
     return ST_OK;
 }
 
-// One full step on a uniform grid (cfl, RK3 flux, then chemistry when DETAILED).
+// Chemistry over dt on every cell of a uniform grid (AoS state).
+template <class S>
+int chemistry_cells(const Phys<S>& ph, int n, std::vector<S>& U, std::vector<S>& T, const S& dt) {
+    int status = ST_OK;
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < n; ++c) {
+        int s2 = cell_chemistry(ph, &U[(size_t)c * ph.nU], T[c], dt);
+        if (s2) {
+#pragma omp critical
+            status = s2;
+        }
+    }
+    return status;
+}
+
+// One full step on a uniform grid: dt from the state at the step start, RK3 flux
+// update, chemistry (DETAILED) after it (Lie) or half before and half after (Strang).
 template <class S>
 int step_uniform(const GridCfg& g, const Phys<S>& ph, const TimeCfg& tc, const BCStates<S>& bcs,
                  std::vector<S>& U, std::vector<S>& T, double& t, double* dt_used,
@@ -665,6 +683,13 @@ int step_uniform(const GridCfg& g, const Phys<S>& ph, const TimeCfg& tc, const B
     if (dt_used) *dt_used = val(dt);
     if (probe_dt) probe_dt->assign(1, dt);
     if (!(val(dt) > 0.0)) return ST_OK;
+    // chemistry interval: dt (Lie) or dt/2 on both sides of the stages (Strang)
+    const bool strang = tc.split == 1 && ph.model == MODEL_DETAILED;
+    const S dtc = strang ? S(0.5) * dt : dt;
+    if (strang) {
+        st = chemistry_cells(ph, n, U, T, dtc);
+        if (st) return st;
+    }
     std::vector<S> U0 = U, Us = U, Ts = T, L, Un((size_t)n * nU), Tn(n);
     for (int stage = 1; stage <= 3; ++stage) {
         st = rhs_uniform(g, ph, Us.data(), Ts.data(), bcs, L);
@@ -687,16 +712,8 @@ int step_uniform(const GridCfg& g, const Phys<S>& ph, const TimeCfg& tc, const B
         std::swap(Ts, Tn);
     }
     if (ph.model == MODEL_DETAILED) {
-        int status = ST_OK;
-#pragma omp parallel for schedule(static)
-        for (int c = 0; c < n; ++c) {
-            int s2 = cell_chemistry(ph, &Us[(size_t)c * nU], Ts[c], dt);
-            if (s2) {
-#pragma omp critical
-                status = s2;
-            }
-        }
-        if (status) return status;
+        st = chemistry_cells(ph, n, Us, Ts, dtc);
+        if (st) return st;
     }
     U.swap(Us);
     T.swap(Ts);
@@ -1045,6 +1062,38 @@ int step_blocks(BlockSet& B, const std::vector<Phys<S>>& phys, const TimeCfg& tc
         choose_dt(tc, cm[d], t[d], dt[d]);
         if (dt_out) dt_out[d] = val(dt[d]);
     }
+    // chemistry on the solved cells of every valid block over f * dt (DETAILED)
+    auto chemistry = [&](std::vector<S>& Uc, std::vector<S>& Tc, double f) -> int {
+        int status2 = ST_OK;
+#pragma omp parallel for schedule(dynamic)
+        for (int b = 0; b < nb; ++b) {
+            const BlockRec& r = B.blk[b];
+            if (!r.valid || !(val(dt[r.domain]) > 0.0)) continue;
+            const S dtc = f * dt[r.domain];
+            for (int j = 0; j < r.ny; ++j)
+                for (int i = 0; i < r.nx; ++i) {
+                    if (!solved(b, i, j)) continue;
+                    long long c = r.offset + (long long)j * r.nx + i;
+                    S u[64];
+                    for (int f2 = 0; f2 < nU; ++f2) u[f2] = Uc[(size_t)f2 * pool + c];
+                    int st = cell_chemistry(phys[r.domain], u, Tc[c], dtc);
+                    for (int f2 = 0; f2 < nU; ++f2) Uc[(size_t)f2 * pool + c] = u[f2];
+                    if (st) {
+#pragma omp critical
+                        status2 = st;
+                    }
+                }
+        }
+        return status2;
+    };
+    const bool detailed = B.nU > 0 && phys[0].model == MODEL_DETAILED;
+    const bool strang = detailed && tc.split == 1;
+    if (strang) {
+        // first half; stage 1's alpha from the state it leaves
+        status = chemistry(Upool, Tpool, 0.5);
+        if (!status) status = reductions(Upool, Tpool, ax, ay, cm, have);
+        if (status) return status;
+    }
 
     const std::vector<S>* Uin = &Upool;
     const std::vector<S>* Tin = &Tpool;
@@ -1112,26 +1161,8 @@ int step_blocks(BlockSet& B, const std::vector<Phys<S>>& phys, const TimeCfg& tc
         Uin = &Udst;
         Tin = &Tdst;
     }
-    // chemistry on solved cells (DETAILED)
-    if (B.nU > 0 && phys[0].model == MODEL_DETAILED) {
-#pragma omp parallel for schedule(dynamic)
-        for (int b = 0; b < nb; ++b) {
-            const BlockRec& r = B.blk[b];
-            if (!r.valid || !(val(dt[r.domain]) > 0.0)) continue;
-            for (int j = 0; j < r.ny; ++j)
-                for (int i = 0; i < r.nx; ++i) {
-                    if (!solved(b, i, j)) continue;
-                    long long c = r.offset + (long long)j * r.nx + i;
-                    S u[64];
-                    for (int f = 0; f < nU; ++f) u[f] = Uout[(size_t)f * pool + c];
-                    int st = cell_chemistry(phys[r.domain], u, Tout[c], dt[r.domain]);
-                    for (int f = 0; f < nU; ++f) Uout[(size_t)f * pool + c] = u[f];
-                    if (st) {
-#pragma omp critical
-                        status = st;
-                    }
-                }
-        }
+    if (detailed) {
+        status = chemistry(Uout, Tout, strang ? 0.5 : 1.0);
         if (status) return status;
     }
     status = restrict_and_refill(B, phys, bcU, bcT, Uout, Tout, dt);
@@ -1215,6 +1246,31 @@ int step_blocks_crossover(BlockSet& B, const std::vector<Phys<S>>& phys, const T
     auto advance_level = [&](int lev) -> int {
         std::vector<S> dtl(nd);
         for (int d = 0; d < nd; ++d) dtl[d] = dt0[d] * std::ldexp(1.0, -lev);
+        // Strang: the level's first half chemistry step, in place
+        const bool strang = tc.split == 1 && nU > 0 && phys[0].model == MODEL_DETAILED;
+        if (strang) {
+            int status1 = ST_OK;
+#pragma omp parallel for schedule(dynamic)
+            for (int b = 0; b < nb; ++b) {
+                const BlockRec& r = B.blk[b];
+                if (!r.valid || r.level != lev || !(val(dtl[r.domain]) > 0.0)) continue;
+                const S dtc = 0.5 * dtl[r.domain];
+                for (int j = 0; j < r.ny; ++j)
+                    for (int i = 0; i < r.nx; ++i) {
+                        if (B.ring[b][(size_t)j * r.nx + i]) continue;
+                        const long long c = r.offset + (long long)j * r.nx + i;
+                        S u[64];
+                        for (int f = 0; f < nU; ++f) u[f] = Upool[(size_t)f * pool + c];
+                        const int st = cell_chemistry(phys[r.domain], u, Tpool[c], dtc);
+                        for (int f = 0; f < nU; ++f) Upool[(size_t)f * pool + c] = u[f];
+                        if (st) {
+#pragma omp critical
+                            status1 = st;
+                        }
+                    }
+            }
+            if (status1) return status1;
+        }
         std::vector<S> Unew = Upool, Tnew = Tpool;
         const std::vector<S>* Uin = &Upool;
         const std::vector<S>* Tin = &Tpool;
@@ -1294,7 +1350,8 @@ int step_blocks_crossover(BlockSet& B, const std::vector<Phys<S>>& phys, const T
                     S u[64];
                     for (int f = 0; f < nU; ++f) u[f] = Unew[(size_t)f * pool + c];
                     if (phys[r.domain].model == MODEL_DETAILED) {
-                        const int st = cell_chemistry(phys[r.domain], u, Tnew[c], dtl[r.domain]);
+                        const S dtc = strang ? 0.5 * dtl[r.domain] : dtl[r.domain];
+                        const int st = cell_chemistry(phys[r.domain], u, Tnew[c], dtc);
                         if (st) {
 #pragma omp critical
                             status3 = st;
@@ -1338,7 +1395,7 @@ struct OMech {
 };
 struct OPhys { int model; double gamma, R, Q, Ea, k; };
 struct OGrid { int nx, ny; double dx, dy; int bc[4]; };
-struct OTime { double cfl, dt_fixed, t_end; };
+struct OTime { double cfl, dt_fixed, t_end; int split, pad; };
 
 MechData mech_from(const OMech* m) {
     MechData d;
@@ -1542,7 +1599,8 @@ int oracle_step(const OGrid* g, const OPhys* p, const OMech* m, const double* bc
     if (gc.nx < 1 || gc.ny < 1) return ST_EINVAL;
     BCStates<double> bcs;
     if (bc_states_from(ph, g, bc_prim, bcs)) return ST_EINVAL;
-    TimeCfg tc{tm->cfl, tm->dt_fixed, tm->t_end};
+    if (tm->split != 0 && (tm->split != 1 || ph.model != MODEL_DETAILED)) return ST_EINVAL;
+    TimeCfg tc{tm->cfl, tm->dt_fixed, tm->t_end, tm->split};
     long long n = (long long)gc.nx * gc.ny;
     std::vector<double> Ua, Ta(T, T + n);
     soa_to_aos(ph.nU, n, U, Ua);
@@ -1566,6 +1624,7 @@ int oracle_step_blocks(int model, const OMech* m, int ndom, const ODomain* doms,
                        const double* bc_prim /* [ndom][4][nU] */, int nblocks,
                        const BlockRec* blocks, long long pool, const OTime* tm, double* U,
                        double* T, int nsteps, double* t_dom, double* dt_log, int crossover) {
+    if (tm->split != 0 && (tm->split != 1 || model != MODEL_DETAILED)) return ST_EINVAL;
     MechData md = mech_from(m);
     BlockSet B;
     B.pool = pool;
@@ -1609,7 +1668,7 @@ int oracle_step_blocks(int model, const OMech* m, int ndom, const ODomain* doms,
     std::vector<double> t(t_dom, t_dom + ndom);
     std::vector<double> dts(ndom);
     for (int s = 0; s < nsteps && !st; ++s) {
-        const TimeCfg tc{tm->cfl, tm->dt_fixed, tm->t_end};
+        const TimeCfg tc{tm->cfl, tm->dt_fixed, tm->t_end, tm->split};
         st = crossover ? step_blocks_crossover(B, phys, tc, bcU, bcT, Up, Tp, t, dts.data())
                        : step_blocks(B, phys, tc, bcU, bcT, Up, Tp, t, dts.data());
         if (dt_log)

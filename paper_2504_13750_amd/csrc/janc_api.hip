@@ -44,9 +44,10 @@ struct GraphKey {
     const double *U, *T, *t, *dt_log;
     int cap;
     double cfl, dt_fixed, t_end;
+    int split;
     bool operator==(const GraphKey& o) const {
         return U == o.U && T == o.T && t == o.t && dt_log == o.dt_log && cap == o.cap &&
-               cfl == o.cfl && dt_fixed == o.dt_fixed && t_end == o.t_end;
+               cfl == o.cfl && dt_fixed == o.dt_fixed && t_end == o.t_end && split == o.split;
     }
 };
 
@@ -106,6 +107,16 @@ janc_status fail(janc_ctx* c, janc_status code, const char* fmt, ...) {
 
 janc_status hipfail(janc_ctx* c, hipError_t e, const char* what) {
     return fail(c, JANC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Time settings common to every stepping entry point.
+janc_status check_time(janc_ctx* c, const janc_time* tm) {
+    if (!(tm->dt_fixed > 0.0) && !(tm->cfl > 0.0)) return fail(c, JANC_EINVAL, "need cfl > 0 or dt_fixed > 0");
+    if (tm->split != JANC_SPLIT_LIE && tm->split != JANC_SPLIT_STRANG)
+        return fail(c, JANC_EINVAL, "split must be JANC_SPLIT_LIE or JANC_SPLIT_STRANG");
+    if (tm->split == JANC_SPLIT_STRANG && c->model != DETAILED)
+        return fail(c, JANC_EINVAL, "Strang splitting needs a model with chemistry (detailed)");
+    return JANC_OK;
 }
 
 #define HIPCHK(ctx, expr, what)                      \
@@ -422,8 +433,8 @@ janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, con
     if ((st = upload(c, &P->dfine, fl))) return st;
     if ((st = upload(c, &P->dring, P->ring_blocks))) return st;
     P->red_stride = 2 * P->nunits + nd;
-    const int ntrip = (flags & JANC_PLAN_CROSSOVER) ? P->maxlev + 1 : 1;   // slot triples
-    if ((st = dalloc(c, &P->dred, (size_t)3 * ntrip * P->red_stride))) return st;
+    const int ntrip = (flags & JANC_PLAN_CROSSOVER) ? P->maxlev + 1 : 1;   // slot sets
+    if ((st = dalloc(c, &P->dred, (size_t)RED_BUFS * ntrip * P->red_stride))) return st;
     if ((st = dalloc(c, &P->ddt, nd))) return st;
     if ((st = dalloc(c, &P->dstep, 1))) return st;
     if ((st = dalloc(c, &P->U1, (size_t)nU * pool))) return st;
@@ -487,6 +498,7 @@ StageArgs base_args(janc_plan* P, const janc_time* tm, double* U, double* T, dou
     a.step = P->dstep;
     a.dt_log_cap = cap;
     a.tm = TimeArgs{tm->cfl, tm->dt_fixed, tm->t_end};
+    a.strang = (tm->split == JANC_SPLIT_STRANG && P->ctx->model == DETAILED) ? 1 : 0;
     a.status = P->ctx->dstatus;
     if (P->flags & JANC_PLAN_CROSSOVER) {
         a.cross = 1;
@@ -497,11 +509,28 @@ StageArgs base_args(janc_plan* P, const janc_time* tm, double* U, double* T, dou
     return a;
 }
 
-// Level l's slot triple in the crossover advance.
+// Level l's slot set in the crossover advance.
 Reduce level_red(const janc_plan* P, const StageArgs& base, int l) {
     Reduce r = base.red;
-    if (base.cross) r.buf = P->dred + (size_t)l * 3 * P->red_stride;
+    if (base.cross) r.buf = P->dred + (size_t)l * RED_BUFS * P->red_stride;
     return r;
+}
+
+// The first half chemistry launch of a Strang-split step (in place on U, T).
+hipError_t launch_chem_first_half(janc_plan* P, const StageArgs& base, const Reduce& red, double* U,
+                                  double* T, int first_tile, int ntiles, int xfirst, hipStream_t s) {
+    StageArgs a = base;
+    a.red = red;
+    a.stage = 0;
+    a.Uin = U;
+    a.Uout = U;
+    a.Tin = T;
+    a.Tout = T;
+    a.tiles = P->dtiles + first_tile;
+    a.ntiles = ntiles;
+    a.chem_phase = 1;
+    a.xfirst = xfirst;
+    return launch_chem(P->ctx->model, P->ctx->ns, P->tile_w, a, s);
 }
 
 // One crossover step (Fig. 2a, Alg. 2): two steps of level l + 1 before each step of
@@ -522,6 +551,11 @@ hipError_t enqueue_crossover(janc_plan* P, const StageArgs& base, double* U, dou
         const bool last_of_level = done[l] == (1 << l) - 1;
         ++done[l];
         if (n == 0 || e != hipSuccess) return;
+        if (base.strang) {
+            e = launch_chem_first_half(P, base, level_red(P, base, l), U, T, P->lev_first[l], n,
+                                       first ? 1 : 0, s);
+            first = false;
+        }
         for (int st = 1; st <= 3 && e == hipSuccess; ++st) {
             StageArgs a = base;
             a.red = level_red(P, base, l);
@@ -549,6 +583,7 @@ hipError_t enqueue_crossover(janc_plan* P, const StageArgs& base, double* U, dou
             a.ntiles = n;
             a.xlast = (l == 0) ? 1 : 0;
             a.xskip_cov = last_of_level ? 1 : 0;
+            a.chem_phase = base.strang ? 2 : 0;
             e = launch_chem(model, ns, P->tile_w, a, s);
         }
     };
@@ -589,6 +624,7 @@ hipError_t enqueue_step(janc_plan* P, const StageArgs& base, double* U, double* 
     double* Tin[3] = {T, P->T1, P->T2};
     double* Tout[3] = {P->T1, P->T2, T};
     hipError_t e = hipSuccess;
+    if (base.strang) e = launch_chem_first_half(P, base, base.red, U, T, 0, base.ntiles, 0, s);
     for (int st = 1; st <= 3 && e == hipSuccess; ++st) {
         StageArgs a = base;
         a.stage = st;
@@ -610,6 +646,7 @@ hipError_t enqueue_step(janc_plan* P, const StageArgs& base, double* U, double* 
     a.Uout = U;
     a.Tin = T;
     a.Tout = T;
+    a.chem_phase = base.strang ? 2 : 0;
     if (e == hipSuccess && model == DETAILED) e = launch_chem(model, ns, P->tile_w, a, s);
     for (int l = P->maxlev; l >= 1 && e == hipSuccess; --l)
         e = launch_restrict(model, ns, a, P->dfine + P->fine_off[l], (int)P->fine[l].size(), s);
@@ -655,7 +692,7 @@ janc_status run_steps(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U,
         for (int n = 0; n < nsteps; ++n) HIPCHK(c, enqueue_step(P, base, U, T, s), "step launch");
         return JANC_OK;
     }
-    const GraphKey key{U, T, t, dt_log, nsteps, tm->cfl, tm->dt_fixed, tm->t_end};
+    const GraphKey key{U, T, t, dt_log, nsteps, tm->cfl, tm->dt_fixed, tm->t_end, tm->split};
     if (!P->have_graph || !(P->gkey == key)) {
         drop_graph(P);
         hipStream_t cs;
@@ -1084,14 +1121,14 @@ janc_status janc_step_blocks(janc_ctx* c, janc_plan* P, const janc_time* tm, dou
                              int nsteps, double* t, void* stream) {
     if (!c || !P || !tm || !U || !T || !t || nsteps < 0) return fail(c, JANC_EINVAL, "bad arguments");
     if (P->ctx != c) return fail(c, JANC_EINVAL, "plan belongs to another context");
-    if (!(tm->dt_fixed > 0.0) && !(tm->cfl > 0.0)) return fail(c, JANC_EINVAL, "need cfl > 0 or dt_fixed > 0");
+    if (janc_status st = check_time(c, tm)) return st;
     return run_steps(c, P, tm, U, T, nsteps, t, nullptr, (hipStream_t)stream);
 }
 
 janc_status janc_step(janc_ctx* c, const janc_grid* g, const janc_physics* ph, const janc_time* tm,
                       double* U, double* T, int nsteps, double* t, double* dt_log, void* stream) {
     if (!c || !g || !ph || !tm || !U || !T || !t || nsteps < 0) return fail(c, JANC_EINVAL, "bad arguments");
-    if (!(tm->dt_fixed > 0.0) && !(tm->cfl > 0.0)) return fail(c, JANC_EINVAL, "need cfl > 0 or dt_fixed > 0");
+    if (janc_status st = check_time(c, tm)) return st;
     janc_status st = uniform_plan(c, g, ph);
     if (st) return st;
     return run_steps(c, c->uplan, tm, U, T, nsteps, t, dt_log, (hipStream_t)stream);
@@ -1103,6 +1140,8 @@ janc_status janc_profile_step(janc_ctx* c, janc_plan* P, const janc_time* tm, do
     if (P->ctx != c) return fail(c, JANC_EINVAL, "plan belongs to another context");
     if (P->flags & JANC_PLAN_CROSSOVER)
         return fail(c, JANC_EINVAL, "per-kernel profiling times the synchronous advance");
+    if (janc_status st = check_time(c, tm)) return st;
+    if (tm->split != JANC_SPLIT_LIE) return fail(c, JANC_EINVAL, "per-kernel profiling times the Lie-split step");
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
     const StageArgs base = base_args(P, tm, U, T, t, nullptr, 0);
@@ -1169,6 +1208,7 @@ janc_status janc_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph
     if (!c || !g || !ph || !tm || !W0 || !loss || !dL_dW0 || !dL_dtheta || nsteps < 1 ||
         ckpt_every < 1 || nprobes < 0 || (nprobes > 0 && (!probe_cell || !probe_w)))
         return fail(c, JANC_EINVAL, "bad arguments");
+    if (janc_status st = check_time(c, tm)) return st;
     return run_adjoint(c, g, ph, tm, W0, nsteps, ckpt_every, nprobes, probe_cell, probe_w, loss,
                        dL_dW0, dL_dtheta, (hipStream_t)stream);
 }

@@ -286,7 +286,7 @@ __device__ __forceinline__ double step_dt(const StageArgs& a, int d, int bin) {
     } else if (a.cross) {
         double m = 0.0;
         for (int l = 0; l < a.xlevels; ++l)
-            m = fmax(m, __longlong_as_double((long long)a.xred[((size_t)l * 3 + bin) * a.red.stride +
+            m = fmax(m, __longlong_as_double((long long)a.xred[((size_t)l * RED_BUFS + bin) * a.red.stride +
                                                                2 * a.red.nunits + d]));
         dt = a.tm.cfl / m;
     } else {
@@ -329,20 +329,23 @@ __device__ __forceinline__ double cfl_bound(const StageArgs& a, CDom& D, int lev
 }
 
 // Per-launch bookkeeping done by workgroup 0: rotate reduction buffers, dt and t.
+// This step's dt per domain (from buffer 0's CFL slots) into a.dt and the dt log.
+__device__ void record_dt(const StageArgs& a) {
+    const int step = *a.step;
+    for (int d = threadIdx.x; d < a.ndom; d += WG) {
+        const double dt = step_dt(a, d, 0);
+        a.dt[d] = dt;
+        if (a.dt_log && step < a.dt_log_cap) a.dt_log[(size_t)step * a.ndom + d] = dt;
+    }
+}
+
 __device__ void stage_bookkeeping(const StageArgs& a, int owner_launch) {
     const int s = a.stage;
     const int bclear = (s + 1) % 3;
     for (int q = threadIdx.x; q < a.red.stride; q += WG) a.red.buf[(size_t)bclear * a.red.stride + q] = 0ull;
     if (a.cross) owner_launch = a.xfirst;
     if (!owner_launch) return;
-    if (s == 1) {
-        const int step = *a.step;
-        for (int d = threadIdx.x; d < a.ndom; d += WG) {
-            const double dt = step_dt(a, d, 0);
-            a.dt[d] = dt;
-            if (a.dt_log && step < a.dt_log_cap) a.dt_log[(size_t)step * a.ndom + d] = dt;
-        }
-    }
+    if (s == 1 && !a.strang) record_dt(a);   // under Strang splitting the first chemistry launch does
 }
 
 __device__ void step_finish(const StageArgs& a) {

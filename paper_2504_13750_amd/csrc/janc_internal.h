@@ -73,6 +73,11 @@ struct DevMech {
 // (domain, level) unit the maxima of |u|+c and |v|+c (Eq. 4.11), per domain
 // the CFL bound max((|u|+c)/dx + (|v|+c)/dy). Non-negative doubles are stored
 // by bit pattern, so an unsigned integer max is the floating-point max.
+// Reduction slot buffers per slot set: buffers 0-2 rotate through the RK stages
+// (stage s reads s - 1, writes s mod 3, clears s + 1 mod 3); buffer 3 carries the
+// maxima of the first half chemistry step to stage 1 under Strang splitting.
+constexpr int RED_BUFS = 4;
+
 struct Reduce {
     unsigned long long* buf;
     int stride;
@@ -110,13 +115,15 @@ struct StageArgs {
     int dt_log_cap;
     TimeArgs tm;
     unsigned* status;
+    int strang;               // Strang splitting: chemistry over dt/2 before and after the stages
+    int chem_phase;           // chemistry launch: 0 whole dt, 1 first half, 2 second half
     // crossover advance (per-level launches, dt_l = dt_0 / 2^l); all zero otherwise
     int cross;
     int xfirst;               // first launch of the step: computes dt_0
     int xlast;                // last launch of the step: advances t and the step counter
     int xskip_cov;            // last step of this level in the step: covered cells leave the maxima
     int xlevels;              // levels with reduction slot triples
-    unsigned long long* xred; // all levels' slot triples (level l at l * 3 * red.stride)
+    unsigned long long* xred; // all levels' slot sets (level l at l * RED_BUFS * red.stride)
     const double* Tbase;      // T of the pool (coarser levels' current state)
 };
 

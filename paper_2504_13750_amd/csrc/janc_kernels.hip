@@ -82,7 +82,7 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
     CDom& D = cdom(a.dom, B.domain);
     const int lev = B.level;
     const int stage = a.stage;
-    const int bin = stage - 1, bout = stage % 3;
+    const int bin = (stage == 1 && a.strang) ? 3 : stage - 1, bout = stage % 3;
     // crossover advance: dt_l = dt_0 / 2^l, dt_0 formed by the first launch of the step
     const double dt = a.cross ? ldexp((a.xfirst && stage == 1) ? step_dt(a, B.domain, 0)
                                                                : a.dt[B.domain], -lev)
@@ -512,9 +512,23 @@ __global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
     CMech* mech = cmech(a.mech);
     const CellRef r = tile_cell(a, tile, B);
     const int lev = B.level, slot = D.slot0 + lev;
-    const double dt = a.cross ? ldexp(a.dt[B.domain], -lev) : a.dt[B.domain];
+    // phase 0: the whole dt after the stages (Lie); phase 1: dt/2 before stage 1, this
+    // launch forms the step's dt; phase 2: dt/2 after stage 3 (Strang, Sec. 4.2)
+    const int phase = a.chem_phase;
+    const double dstep = a.cross ? ldexp((phase == 1 && a.xfirst) ? step_dt(a, B.domain, 0)
+                                                                   : a.dt[B.domain], -lev)
+                                 : (phase == 1) ? step_dt(a, B.domain, 0) : a.dt[B.domain];
+    const double dt = (phase == 0) ? dstep : 0.5 * dstep;
     const double idx = (double)(1 << lev) / D.dx0, idy = (double)(1 << lev) / D.dy0;
-    if (blockIdx.x == 0 && (!a.cross || a.xlast)) step_finish(a);
+    if (blockIdx.x == 0) {
+        if (phase == 1) {
+            if (!a.cross || a.xfirst) record_dt(a);
+        } else if (!a.cross || a.xlast) {
+            step_finish(a);
+        }
+    }
+    if (phase == 2)   // buffer 3 was read by stage 1; clean for the next step's first half
+        for (int q = threadIdx.x; q < a.red.stride; q += WG) a.red.buf[(size_t)3 * a.red.stride + q] = 0ull;
     if (!(dt > 0.0)) return;
     double sx = 0.0, sy = 0.0, sc = 0.0;
     unsigned st = 0u;
@@ -547,7 +561,8 @@ __global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
         st |= owner_state<DETAILED, NU>(u, T, D, mech, Tn, c, vx, vy);
         a.Tout[r.c] = Tn;
         if (st) atomicOr(a.status, st);
-        const bool skip = B.fine_child && (!a.cross || a.xskip_cov) &&
+        // the first half's maxima are stage 1's alpha over all solved cells
+        const bool skip = phase != 1 && B.fine_child && (!a.cross || a.xskip_cov) &&
                           covered_by_finer(a, D, lev, r.I, r.J);
         if (!st && !skip) {
             sx = fabs(vx) + c;
@@ -555,7 +570,8 @@ __global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
             sc = cfl_bound(a, D, lev, sx, sy, idx, idy);
         }
     }
-    publish_max3(a.red, 0, 2 * slot, 2 * slot + 1, 2 * a.red.nunits + B.domain, sx, sy, sc, scratch);
+    publish_max3(a.red, (phase == 1) ? 3 : 0, 2 * slot, 2 * slot + 1, 2 * a.red.nunits + B.domain, sx,
+                 sy, sc, scratch);
 }
 
 // Four-to-one restriction (Sec. 3.1.4 coarsening): each coarse cell under a
@@ -702,7 +718,7 @@ hipError_t launch_zero_int(int* p, hipStream_t s) {
 }
 
 hipError_t launch_clear_reduce(const Reduce& r, int which, hipStream_t s) {
-    const int n = (which < 0) ? 3 * r.stride : r.stride;
+    const int n = (which < 0) ? RED_BUFS * r.stride : r.stride;
     unsigned long long* p = (which < 0) ? r.buf : r.buf + (size_t)which * r.stride;
     clear_kernel<<<1, WG, 0, s>>>(p, n);
     return hipGetLastError();

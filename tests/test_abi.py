@@ -35,9 +35,39 @@ def test_struct_layouts_match_header():
     from paper_2504_13750_amd import _lib as L
     assert ctypes.sizeof(L.janc_block) == 40
     assert ctypes.sizeof(L.janc_physics) == 40
-    assert ctypes.sizeof(L.janc_time) == 24
+    assert ctypes.sizeof(L.janc_time) == 32
     assert ctypes.sizeof(L.janc_grid) == 8 + 16 + 16 + 4 * 16 * 8
     assert ctypes.sizeof(L.janc_mech) == 8 + 12 * 8
+
+
+def test_struct_layouts_match_c_compiler(tmp_path):
+    """sizeof and field offsets of the binding's structs equal those the C compiler
+    gives the header's declarations."""
+    import shutil
+    import subprocess
+    from paper_2504_13750_amd import _lib as L
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"janc_block": L.janc_block, "janc_physics": L.janc_physics,
+               "janc_time": L.janc_time, "janc_grid": L.janc_grid, "janc_mech": L.janc_mech,
+               "janc_domain": L.janc_domain}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "janc.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            lines.append(f'printf("{name}.{f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f in cls._fields_:
+            assert int(got[f"{name}.{f[0]}"]) == getattr(cls, f[0]).offset, (name, f[0])
 
 
 def test_block_dtype_matches_cases():

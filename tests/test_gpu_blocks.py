@@ -30,7 +30,8 @@ def _cmp_blocks(bcase, nsteps, tol=TOL, crossover=False, **kw):
         kw["flags"] = kw.get("flags", 0) | janc.PLAN_CROSSOVER
     Ug, Tg, tg = run_blocks(bcase, nsteps, **kw)
     Uo, To = oracle.block_state(bcase)
-    Uo, To, to, _, _ = oracle.step_blocks(bcase, Uo, To, nsteps, crossover=crossover)
+    Uo, To, to, _, _ = oracle.step_blocks(bcase, Uo, To, nsteps, crossover=crossover,
+                                          strang=kw.get("split", 0) == 1)
     valid = np.zeros(bcase.pool_cells, bool)
     for b in bcase.blocks[bcase.blocks["valid"] != 0]:
         valid[b["offset"]:b["offset"] + b["nx"] * b["ny"]] = True
@@ -175,3 +176,21 @@ def test_crossover_per_block_rejected():
                  janc.PLAN_CROSSOVER | janc.PLAN_PER_BLOCK)
     assert ei.value.code == -1
     ctx.close()
+
+
+# ------------------------------------------------------------------ Strang splitting
+def test_strang_amr_detailed_vs_oracle():
+    _cmp_blocks(_small_detailed_amr(), 3, split=janc.SPLIT_STRANG)
+
+
+def test_strang_crossover_amr_detailed_vs_oracle():
+    _cmp_blocks(_small_detailed_amr(), 2, crossover=True, split=janc.SPLIT_STRANG)
+
+
+def test_strang_launch_forms_agree_bitwise():
+    bc = _small_detailed_amr()
+    Ua, Ta, ta = run_blocks(bc, 3, split=janc.SPLIT_STRANG)
+    Ub, Tb, tb = run_blocks(bc, 3, split=janc.SPLIT_STRANG, flags=janc.PLAN_NO_GRAPH)
+    Uc, Tc, tc = run_blocks(bc, 3, split=janc.SPLIT_STRANG, flags=janc.PLAN_PER_BLOCK)
+    assert np.array_equal(Ua, Ub) and np.array_equal(Ta, Tb) and np.array_equal(ta, tb)
+    assert np.array_equal(Ua, Uc) and np.array_equal(Ta, Tc) and np.array_equal(ta, tc)

@@ -24,6 +24,7 @@ def _compare(case, nsteps, tol=TOL, **kw):
     Ug, Tg, tg, dg = run_uniform(case, nsteps, **kw)
     Uo, To = oracle.case_state(case)
     okw = {k: v for k, v in kw.items() if k in ("dt_fixed", "t_end", "cfl")}
+    okw["strang"] = kw.get("split", 0) == 1
     Uo, To, to, do, _ = oracle.step(case, Uo, To, nsteps, **okw)
     e = rel_err(Ug, Uo)
     eT = rel_err(Tg[None], To[None])[0]
@@ -155,3 +156,16 @@ def test_status_flag_on_negative_density():
     with pytest.raises(janc.JancError) as ei:
         run_uniform(c, 1)
     assert ei.value.code == -6
+
+
+def test_detailed_front_strang_splitting():
+    c = detailed_front_case(nx=48, ny=40)
+    _compare(c, 4, split=1)
+
+
+def test_strang_rejected_without_chemistry():
+    import paper_2504_13750_amd as janc
+    c = detonation_tube_case(nx=16, ny=8, seed=3)
+    with pytest.raises(janc.JancError) as ei:
+        run_uniform(c, 1, split=1)
+    assert ei.value.code == -1
