@@ -206,6 +206,48 @@ janc_status janc_step_blocks(janc_ctx *ctx, janc_plan *plan, const janc_time *ti
                              double *U_pool, double *T_pool, int nsteps, double *t,
                              void *stream);
 
+/* ------------------------------------------------------------------ layer update */
+/* Parameters of the layer update (regridding, Sec. 3.1.2 and 3.1.4, Alg. 2).
+ * A layer-l cell is masked when, on the effective layer-l density field (the
+ * covering layer-l block, else the coarser layer's value, with the boundary
+ * rules outside the domain),
+ *     max(|rho(I+1,J) - rho(I-1,J)|, |rho(I,J+1) - rho(I,J-1)|) > 2 threshold rho(I,J)
+ * (a central-difference density-gradient criterion normalized by the cell's
+ * density and spacing). Each block of the new layer l is cut into fixed
+ * subregions of sub x sub layer-l cells (the last row and column may be
+ * narrower); a subregion becomes a layer-(l+1) block when a masked cell of layer
+ * l lies in it or within `buffer` cells of it (the buffer cells), unless it
+ * contains coarse-fine ring cells of layer l. sub: multiple of 4 in 4..128;
+ * buffer >= 0; threshold >= 0. */
+typedef struct {
+    double threshold;
+    int buffer;
+    int sub;
+} janc_regrid_params;
+
+/* New block table of a plan's domains from the state U_pool (device, the plan's
+ * pool layout; only rho is read). The level-0 blocks are kept in plan order;
+ * layers 1, 2, ... follow, each ordered by parent block and subregion (row by
+ * row); offsets are packed from 0. out (host) [cap] receives the table and
+ * *nout its length; *pool_out the new pool length. When the table needs more
+ * than cap entries the call returns JANC_EINVAL with *nout set to the length
+ * needed. Level-0 blocks of refined domains need sizes that are multiples of 4.
+ * Synchronizes the stream. */
+janc_status janc_regrid(janc_ctx *ctx, janc_plan *plan, const janc_regrid_params *params,
+                        const double *U_pool, janc_block *out, int cap, int *nout,
+                        long long *pool_out, void *stream);
+
+/* Pools of a new plan (same domains) from the state of an old plan: each block
+ * of the new plan with the same domain, level, origin and size as a valid block
+ * of the old plan takes that block's data (U and T, unaltered blocks keep their
+ * data); every other block takes the one-to-four injection of the new plan's
+ * coarser level, which is filled first (refinement operation, Sec. 3.1.4).
+ * Level-0 blocks must all be unaltered. U_old, T_old (device) on the old plan's
+ * pool; U_new, T_new (device) on the new plan's pool. */
+janc_status janc_regrid_fill(janc_ctx *ctx, janc_plan *old_plan, const double *U_old,
+                             const double *T_old, janc_plan *new_plan, double *U_new,
+                             double *T_new, void *stream);
+
 /* Profiling aid: one step of a plan (as in janc_step_blocks, after the call-entry
  * temperature solve) launched without graph capture, with HIP events recorded on
  * `stream` around each launch group. ms (host) [6] receives the durations in

@@ -282,6 +282,58 @@ def ring_flags(bcase):
     return flags
 
 
+class ORegrid(C.Structure):
+    _fields_ = [("threshold", D), ("buffer", I), ("sub", I)]
+
+
+def regrid(bcase, U, threshold, buffer, sub):
+    """New block table of a hierarchy by the density-gradient criterion (layer update of
+    Sec. 3.1.2 / 3.1.4): returns (blocks [BLOCK_DTYPE], pool_cells)."""
+    doms = _domains(bcase)
+    blocks = np.ascontiguousarray(bcase.blocks)
+    ns = bcase.mech.ns if bcase.mech is not None else 0
+    bc_rho = np.zeros((len(bcase.domains), 4))
+    for d, dom in enumerate(bcase.domains):
+        for q in range(4):
+            if dom.bc_prim is not None and dom.bc_prim[q] is not None:
+                bc_rho[d, q] = float(dom.bc_prim[q][0])
+    cfg = ORegrid(float(threshold), int(buffer), int(sub))
+    U = _f64(U)
+    cap = 1024
+    while True:
+        out = np.zeros(cap, dtype=blocks.dtype)
+        n, pool = I(0), C.c_longlong(0)
+        st = lib().oracle_regrid(I(bcase.model), I(ns), I(len(bcase.domains)), doms, _p(bc_rho),
+                                 I(len(blocks)), blocks.ctypes.data_as(C.c_void_p),
+                                 C.c_longlong(bcase.pool_cells), _p(U), C.byref(cfg),
+                                 out.ctypes.data_as(C.c_void_p), I(cap), C.byref(n),
+                                 C.byref(pool))
+        if st == ST_EINVAL and n.value > cap:
+            cap = n.value
+            continue
+        _check(st, "regrid")
+        return out[:n.value].copy(), int(pool.value)
+
+
+def regrid_fill(bcase, U, T, blocks, pool_cells):
+    """Pools of a new table (from regrid): unaltered blocks copied, new blocks injected
+    one-to-four from the new coarser layer. Returns (U, T)."""
+    doms = _domains(bcase)
+    old = np.ascontiguousarray(bcase.blocks)
+    new = np.ascontiguousarray(blocks)
+    ns = bcase.mech.ns if bcase.mech is not None else 0
+    U, T = _f64(U), _f64(T)
+    Un = np.zeros((U.shape[0], pool_cells))
+    Tn = np.zeros(pool_cells)
+    st = lib().oracle_regrid_fill(I(bcase.model), I(ns), I(len(bcase.domains)), doms,
+                                  I(len(old)), old.ctypes.data_as(C.c_void_p),
+                                  C.c_longlong(bcase.pool_cells), _p(U), _p(T), I(len(new)),
+                                  new.ctypes.data_as(C.c_void_p), C.c_longlong(pool_cells),
+                                  _p(Un), _p(Tn))
+    _check(st, "regrid_fill")
+    return Un, Tn
+
+
 # ------------------------------------------------------------------ point functions for pins
 def weno5(f):
     f = _f64(f)

@@ -26,8 +26,10 @@
  *   block tables: same-level ghosts, coarse-fine "external boundary" sync,
  *   four-to-one restriction, synchronous and crossover advance       (Sec. 3.1.3-3.1.4, Alg. 2-3,
  *                                                                     Fig. 2)
+ *   layer update (masked and buffer cells, subregions, one-to-four
+ *   injection of new blocks, unaltered blocks kept)                  (Sec. 3.1.2, 3.1.4, Alg. 2)
  *
- * Readings where the paper is silent (also listed in the design doc):
+ * Readings where the paper is silent:
  *   - WENO5 is the Jiang-Shu form with eps = 1e-6, applied component-wise.
  *   - alpha is recomputed each RK stage over the solved cells of the scope.
  *   - dt = CFL / max((|u|+c)/dx + (|v|+c)/dy) (1-D: the x term only).
@@ -37,6 +39,10 @@
  *   - the coarse-fine boundary uses the ring rule: cells within 3 of an
  *     uncovered in-domain cell are not solved; their value is the injection
  *     of the coarser level at the same stage.
+ *   - Strang splitting, when selected, takes half the chemistry step before
+ *     the RK stages and half after them, with dt from the step-start state.
+ *   - regridding masks cells by a normalized central density difference and
+ *     refines fixed subregions of each block (see the regridding section).
  */
 #include <cmath>
 #include <cstdint>
@@ -1384,6 +1390,134 @@ int step_blocks_crossover(BlockSet& B, const std::vector<Phys<S>>& phys, const T
     return ST_OK;
 }
 
+// ------------------------------------------------------------------ regridding
+// Updating the refinement layers (Sec. 3.1.2 and the layer-update and refinement
+// operations of Sec. 3.1.4; Alg. 2): level by level, each block of the new layer l
+// is divided into fixed subregions of `sub` x `sub` layer-l cells (the last row and
+// column may be narrower); a subregion becomes a layer-(l+1) block when a masked
+// cell of layer l lies in it or within `buffer` cells of it (the buffer cells).
+// A cell is masked by the density-gradient criterion
+//     max(|rho(I+1,J) - rho(I-1,J)|, |rho(I,J+1) - rho(I,J-1)|) > 2 threshold rho(I,J)
+// on the effective layer-l field of the hierarchy before the update (values of the
+// covering layer-l block, else of the coarser layer: the ghost rules of the solver).
+// Subregions that contain coarse-fine ring cells of layer l stay unrefined, so
+// that refined blocks sit on solved cells. Blocks identical to a block of the old
+// table keep their data; new blocks take the one-to-four injection of the new
+// coarser layer.
+struct RegridCfg { double threshold; int buffer, sub; };
+
+// density of layer-l cell (I, J) on the effective field (boundary rules included)
+double effective_density(const BlockSet& B, int d, int l, int I, int J, const double* bc_rho,
+                         const double* U) {
+    Src s;
+    resolve(B, d, l, I, J, s);
+    if (s.cell < 0) return bc_rho[d * 4 + s.side];
+    return U[s.cell];   // field 0 of the pool is rho
+}
+
+bool density_masked(const BlockSet& B, int d, int l, int I, int J, double thr,
+                    const double* bc_rho, const double* U) {
+    const double r = effective_density(B, d, l, I, J, bc_rho, U);
+    const double gx = std::fabs(effective_density(B, d, l, I + 1, J, bc_rho, U) -
+                                effective_density(B, d, l, I - 1, J, bc_rho, U));
+    const double gy = std::fabs(effective_density(B, d, l, I, J + 1, bc_rho, U) -
+                                effective_density(B, d, l, I, J - 1, bc_rho, U));
+    return std::max(gx, gy) > 2.0 * thr * r;
+}
+
+int regrid_table(const BlockSet& B, const double* bc_rho, const double* U, const RegridCfg& cfg,
+                 std::vector<BlockRec>& out) {
+    out.clear();
+    long long off = 0;
+    for (const BlockRec& r : B.blk)
+        if (r.valid && r.level == 0) {
+            BlockRec n = r;
+            n.offset = off;
+            off += (long long)r.nx * r.ny;
+            out.push_back(n);
+        }
+    int maxlev = 0;
+    for (const DomainRec& D : B.dom) maxlev = std::max(maxlev, D.nlevels - 1);
+    for (int l = 0; l < maxlev; ++l) {
+        // the new hierarchy up to layer l, for its ring cells
+        BlockSet N;
+        N.dom = B.dom;
+        N.blk = out;
+        N.pool = off;
+        N.nU = B.nU;
+        int st = build_blockset(N);
+        if (st) return st;
+        const size_t nprev = out.size();
+        for (size_t b = 0; b < nprev; ++b) {
+            const BlockRec r = out[b];
+            if (r.level != l || l + 1 >= B.dom[r.domain].nlevels) continue;
+            const int lw = B.geo[r.domain].lw[l], lh = B.geo[r.domain].lh[l];
+            for (int y0 = 0; y0 < r.ny; y0 += cfg.sub)
+                for (int x0 = 0; x0 < r.nx; x0 += cfg.sub) {
+                    const int w = std::min(cfg.sub, r.nx - x0), h = std::min(cfg.sub, r.ny - y0);
+                    bool ring = false;
+                    for (int j = y0; j < y0 + h && !ring; ++j)
+                        for (int i = x0; i < x0 + w && !ring; ++i) ring = N.ring[b][(size_t)j * r.nx + i] != 0;
+                    if (ring) continue;
+                    bool mask = false;
+                    const int I0 = r.i0 + x0, J0 = r.j0 + y0;
+                    for (int J = J0 - cfg.buffer; J < J0 + h + cfg.buffer && !mask; ++J)
+                        for (int I = I0 - cfg.buffer; I < I0 + w + cfg.buffer && !mask; ++I) {
+                            if (I < 0 || I >= lw || J < 0 || J >= lh) continue;
+                            mask = density_masked(B, r.domain, l, I, J, cfg.threshold, bc_rho, U);
+                        }
+                    if (!mask) continue;
+                    BlockRec n{};
+                    n.domain = r.domain;
+                    n.level = l + 1;
+                    n.i0 = 2 * I0;
+                    n.j0 = 2 * J0;
+                    n.nx = 2 * w;
+                    n.ny = 2 * h;
+                    n.offset = off;
+                    n.valid = 1;
+                    off += (long long)n.nx * n.ny;
+                    out.push_back(n);
+                }
+        }
+    }
+    return ST_OK;
+}
+
+// Data of the new table: copies of unaltered blocks, injection for new ones.
+void regrid_fill(const BlockSet& Bo, const double* Uo, const double* To, const BlockSet& Bn,
+                 double* Un, double* Tn) {
+    const int nU = Bn.nU;
+    for (const BlockRec& r : Bn.blk) {
+        const BlockRec* same = nullptr;
+        for (const BlockRec& q : Bo.blk)
+            if (q.valid && q.domain == r.domain && q.level == r.level && q.i0 == r.i0 &&
+                q.j0 == r.j0 && q.nx == r.nx && q.ny == r.ny)
+                same = &q;
+        for (int j = 0; j < r.ny; ++j)
+            for (int i = 0; i < r.nx; ++i) {
+                const long long c = r.offset + (long long)j * r.nx + i;
+                long long src;
+                const double *Us, *Ts;
+                long long ps;
+                if (same) {
+                    src = same->offset + (long long)j * r.nx + i;
+                    Us = Uo; Ts = To; ps = Bo.pool;
+                } else {
+                    // the parent cell on the new coarser layer (already filled)
+                    const DomainGeo& G = Bn.geo[r.domain];
+                    const int I = (r.i0 + i) >> 1, J = (r.j0 + j) >> 1;
+                    const int pb = G.cover[r.level - 1][(size_t)J * G.lw[r.level - 1] + I];
+                    const BlockRec& P = Bn.blk[pb];
+                    src = P.offset + (long long)(J - P.j0) * P.nx + (I - P.i0);
+                    Us = Un; Ts = Tn; ps = Bn.pool;
+                }
+                for (int f = 0; f < nU; ++f) Un[(size_t)f * Bn.pool + c] = Us[(size_t)f * ps + src];
+                Tn[c] = Ts[src];
+            }
+    }
+}
+
 // ------------------------------------------------------------------ C views
 struct OMech {
     int ns, nr;
@@ -1703,6 +1837,71 @@ int oracle_ring_flags(int model, int ns, int ndom, const ODomain* doms, int nblo
         if (!r.valid) continue;
         for (long long q = 0; q < (long long)r.nx * r.ny; ++q) flags[r.offset + q] = B.ring[b][q];
     }
+    return ST_OK;
+}
+
+static void domains_into(BlockSet& B, int ndom, const ODomain* doms) {
+    for (int d = 0; d < ndom; ++d) {
+        DomainRec r;
+        r.nx = doms[d].nx; r.ny = doms[d].ny; r.dx = doms[d].dx; r.dy = doms[d].dy;
+        for (int q = 0; q < 4; ++q) r.bc[q] = doms[d].bc[q];
+        r.nlevels = doms[d].nlevels;
+        r.gamma = doms[d].gamma; r.R = doms[d].R; r.Q = doms[d].Q; r.Ea = doms[d].Ea; r.k = doms[d].k;
+        B.dom.push_back(r);
+    }
+}
+
+struct ORegrid { double threshold; int buffer, sub; };
+
+// New block table of a hierarchy (pool SoA, field 0 = rho) by the density-gradient
+// criterion: out[cap] receives it with packed offsets, *nout its length (when it
+// exceeds cap the call returns ST_EINVAL), *pool_out the new pool size. bc_rho
+// [ndom][4]: density of each Dirichlet side.
+int oracle_regrid(int model, int ns, int ndom, const ODomain* doms, const double* bc_rho,
+                  int nblocks, const BlockRec* blocks, long long pool, const double* U,
+                  const ORegrid* cfg, BlockRec* out, int cap, int* nout, long long* pool_out) {
+    if (!(cfg->threshold >= 0.0) || cfg->buffer < 0 || cfg->sub < 4 || cfg->sub > 128 || cfg->sub % 4)
+        return ST_EINVAL;
+    BlockSet B;
+    B.pool = pool;
+    B.nU = n_fields(model, ns);
+    domains_into(B, ndom, doms);
+    B.blk.assign(blocks, blocks + nblocks);
+    int st = build_blockset(B);
+    if (st) return st;
+    for (const BlockRec& r : B.blk)
+        if (r.valid && r.level == 0 && B.dom[r.domain].nlevels > 1 && ((r.nx | r.ny) & 3))
+            return ST_EINVAL;
+    std::vector<BlockRec> nb;
+    st = regrid_table(B, bc_rho, U, RegridCfg{cfg->threshold, cfg->buffer, cfg->sub}, nb);
+    if (st) return st;
+    *nout = (int)nb.size();
+    *pool_out = 0;
+    for (const BlockRec& r : nb) *pool_out += (long long)r.nx * r.ny;
+    if ((int)nb.size() > cap) return ST_EINVAL;
+    std::copy(nb.begin(), nb.end(), out);
+    return ST_OK;
+}
+
+// Pools of a new table from the old hierarchy (see regrid_fill).
+int oracle_regrid_fill(int model, int ns, int ndom, const ODomain* doms, int nold,
+                       const BlockRec* old, long long pool_old, const double* Uold,
+                       const double* Told, int nnew, const BlockRec* nw, long long pool_new,
+                       double* Unew, double* Tnew) {
+    BlockSet Bo, Bn;
+    Bo.pool = pool_old;
+    Bn.pool = pool_new;
+    Bo.nU = Bn.nU = n_fields(model, ns);
+    domains_into(Bo, ndom, doms);
+    domains_into(Bn, ndom, doms);
+    Bo.blk.assign(old, old + nold);
+    Bn.blk.assign(nw, nw + nnew);
+    int st = build_blockset(Bo);
+    if (!st) st = build_blockset(Bn);
+    if (st) return st;
+    for (int b = 1; b < nnew; ++b)
+        if (nw[b].level < nw[b - 1].level) return ST_EINVAL;   // coarser layers first
+    regrid_fill(Bo, Uold, Told, Bn, Unew, Tnew);
     return ST_OK;
 }
 

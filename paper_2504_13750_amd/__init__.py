@@ -232,6 +232,37 @@ class Context:
                                              _dptr(t, plan.ndom, "t"),
                                              C.c_void_p(_stream_handle(stream))))
 
+    def regrid(self, plan, U, threshold, buffer, sub, stream=None):
+        """Layer update of a plan's hierarchy from the state U (janc_regrid): returns the
+        new block table (BLOCK_DTYPE records, offsets packed) and its pool length."""
+        params = L.janc_regrid_params(float(threshold), int(buffer), int(sub))
+        cap = max(1024, 4 * int(plan.stats()["blocks"]))
+        while True:
+            out = np.zeros(cap, dtype=BLOCK_DTYPE)
+            n, pool = C.c_int(0), C.c_longlong(0)
+            st = L.lib().janc_regrid(self.h, plan.h, C.byref(params),
+                                     _dptr(U, self.nfields * plan.pool_cells, "U"),
+                                     out.ctypes.data_as(C.c_void_p), cap, C.byref(n),
+                                     C.byref(pool), C.c_void_p(_stream_handle(stream)))
+            if st == -1 and n.value > cap:
+                cap = n.value
+                continue
+            self._check(st)
+            return out[:n.value].copy(), int(pool.value)
+
+    def regrid_fill(self, old_plan, U, T, new_plan, stream=None):
+        """Pools of new_plan from the state (U, T) of old_plan (janc_regrid_fill): new
+        device tensors (U_new, T_new)."""
+        torch = _torch()
+        Un = torch.empty((self.nfields, new_plan.pool_cells), dtype=torch.float64, device=U.device)
+        Tn = torch.empty(new_plan.pool_cells, dtype=torch.float64, device=U.device)
+        self._check(L.lib().janc_regrid_fill(self.h, old_plan.h,
+                                             _dptr(U, self.nfields * old_plan.pool_cells, "U"),
+                                             _dptr(T, old_plan.pool_cells, "T"), new_plan.h,
+                                             _dptr(Un), _dptr(Tn),
+                                             C.c_void_p(_stream_handle(stream))))
+        return Un, Tn
+
     def profile_step(self, plan, time, U, T, t, stream=None):
         """One step with HIP events around each launch group; returns milliseconds of
         [stage 1, stage 2, stage 3, chemistry, restriction, ring refill]."""

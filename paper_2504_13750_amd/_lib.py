@@ -45,6 +45,10 @@ class janc_block(C.Structure):
 
 assert C.sizeof(janc_block) == 40
 
+
+class janc_regrid_params(C.Structure):
+    _fields_ = [("threshold", D), ("buffer", I), ("sub", I)]
+
 _LIB = None
 
 EXPORTS = {
@@ -66,6 +70,9 @@ EXPORTS = {
                               VP]),
     "janc_adjoint": (I, [VP, C.POINTER(janc_grid), C.POINTER(janc_physics), C.POINTER(janc_time),
                          VP, I, I, I, PI, PD, VP, VP, VP, VP]),
+    "janc_regrid": (I, [VP, VP, C.POINTER(janc_regrid_params), VP, VP, I, C.POINTER(I),
+                        C.POINTER(C.c_longlong), VP]),
+    "janc_regrid_fill": (I, [VP, VP, VP, VP, VP, VP, VP, VP]),
 }
 
 
@@ -81,6 +88,9 @@ def lib():
             raise LibraryMissing(
                 f"{LIB_PATH} not found: build the HIP library first "
                 "(python -m paper_2504_13750_amd.build or __graft_entry__.build())")
+        # One HIP runtime per process: torch brings its own; importing it first makes
+        # libjanc bind to that runtime instead of loading a second one beside it.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in EXPORTS.items():
             fn = getattr(L, name)

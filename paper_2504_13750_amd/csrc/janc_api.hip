@@ -8,6 +8,8 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <array>
+#include <map>
 #include <vector>
 
 #include "../../include/janc.h"
@@ -1012,6 +1014,167 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     return JANC_OK;
 }
 
+// ---------------------------------------------------------------- layer update
+// Candidates are generated layer by layer on the host (subregions of the new
+// layer-l blocks without ring cells), flagged by the density criterion on the
+// device, and the flagged ones become the layer-(l+1) blocks.
+janc_status run_regrid(janc_ctx* c, janc_plan* P, const janc_regrid_params* rp, const double* U,
+                       janc_block* out, int cap, int* nout, long long* pool_out, hipStream_t s) {
+    if (!(rp->threshold >= 0.0) || rp->buffer < 0 || rp->buffer > 4096 || rp->sub < 4 ||
+        rp->sub > 128 || rp->sub % 4)
+        return fail(c, JANC_EINVAL,
+                    "regrid: need threshold >= 0, 0 <= buffer <= 4096, sub a multiple of 4 in 4..128");
+    HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    const int sub = rp->sub;
+    std::vector<janc_block> nb;
+    for (const DevBlock& h : P->hblk)
+        if (h.level == 0) {
+            if (P->hdom[h.domain].nlevels > 1 && (h.nx % 4 || h.ny % 4))
+                return fail(c, JANC_EINVAL, "regrid: level-0 block sizes must be multiples of 4 in refined domains");
+            nb.push_back(janc_block{h.domain, 0, h.i0, h.j0, h.nx, h.ny, 0, 1, 0});
+        }
+    janc_time tm0{};
+    tm0.cfl = 1.0;
+    StageArgs a = base_args(P, &tm0, const_cast<double*>(U), nullptr, nullptr, nullptr, 0);
+    a.Uin = U;
+    RegridCand* dc = nullptr;
+    int* df = nullptr;
+    size_t dcap = 0;
+    auto release = [&]() {
+        if (dc) hipFree(dc);
+        if (df) hipFree(df);
+        dc = nullptr;
+        df = nullptr;
+    };
+    for (int l = 0; l < P->maxlev; ++l) {
+        // 8x8-cell coverage of the new layer l, for its ring cells
+        std::vector<std::vector<int>> tmap(P->ndom);
+        std::vector<int> w8(P->ndom), h8(P->ndom);
+        for (int d = 0; d < P->ndom; ++d) {
+            const DevDomain& D = P->hdom[d];
+            w8[d] = ((D.nx0 << l) + 7) / 8;
+            h8[d] = ((D.twod ? (D.ny0 << l) : 1) + 7) / 8;
+            tmap[d].assign((size_t)w8[d] * h8[d], 0);
+        }
+        for (const janc_block& r : nb)
+            if (r.level == l)
+                for (int y = r.j0 / 8; y < (r.j0 + r.ny + 7) / 8; ++y)
+                    for (int x = r.i0 / 8; x < (r.i0 + r.nx + 7) / 8; ++x) tmap[r.domain][(size_t)y * w8[r.domain] + x] = 1;
+        auto covered = [&](int d, int x, int y) -> bool {
+            const DevDomain& D = P->hdom[d];
+            if (x < 0 || x >= w8[d]) {
+                if (D.bc[0] != BC_PERIODIC) return true;
+                x = (x + w8[d]) % w8[d];
+            }
+            if (y < 0 || y >= h8[d]) {
+                if (D.bc[2] != BC_PERIODIC) return true;
+                y = (y + h8[d]) % h8[d];
+            }
+            return tmap[d][(size_t)y * w8[d] + x] != 0;
+        };
+        auto ring_cell = [&](const janc_block& r, int li, int lj) -> bool {
+            if (r.level == 0) return false;
+            const int d = r.domain, x8 = r.i0 / 8, y8 = r.j0 / 8;
+            return (li < 3 && !covered(d, x8 - 1, y8 + lj / 8)) ||
+                   (li >= r.nx - 3 && !covered(d, x8 + r.nx / 8, y8 + lj / 8)) ||
+                   (lj < 3 && !covered(d, x8 + li / 8, y8 - 1)) ||
+                   (lj >= r.ny - 3 && !covered(d, x8 + li / 8, y8 + r.ny / 8));
+        };
+        std::vector<RegridCand> cand;
+        for (size_t b = 0; b < nb.size(); ++b) {
+            const janc_block r = nb[b];
+            if (r.level != l || l + 1 >= P->hdom[r.domain].nlevels) continue;
+            for (int y0 = 0; y0 < r.ny; y0 += sub)
+                for (int x0 = 0; x0 < r.nx; x0 += sub) {
+                    const int w = std::min(sub, r.nx - x0), h = std::min(sub, r.ny - y0);
+                    bool ring = false;
+                    for (int lj = y0; lj < y0 + h && !ring; ++lj)
+                        for (int li = x0; li < x0 + w && !ring; ++li) ring = ring_cell(r, li, lj);
+                    if (!ring) cand.push_back(RegridCand{r.domain, r.i0 + x0, r.j0 + y0, w, h, 0});
+                }
+        }
+        if (cand.empty()) continue;
+        if (cand.size() > dcap) {
+            release();
+            dcap = cand.size();
+            janc_status st = dalloc(c, &dc, dcap);
+            if (!st) st = dalloc(c, &df, dcap);
+            if (st) {
+                release();
+                return st;
+            }
+        }
+        std::vector<int> flags(cand.size());
+        hipError_t e = hipMemcpyAsync(dc, cand.data(), sizeof(RegridCand) * cand.size(), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = launch_regrid_flag(a, dc, (int)cand.size(), l, rp->buffer, rp->threshold, df, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(flags.data(), df, sizeof(int) * cand.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            release();
+            return hipfail(c, e, "regrid flags");
+        }
+        for (size_t k = 0; k < cand.size(); ++k)
+            if (flags[k])
+                nb.push_back(janc_block{cand[k].domain, l + 1, 2 * cand[k].i0, 2 * cand[k].j0,
+                                        2 * cand[k].w, 2 * cand[k].h, 0, 1, 0});
+    }
+    release();
+    long long off = 0;
+    for (janc_block& r : nb) {
+        r.offset = off;
+        off += (long long)r.nx * r.ny;
+    }
+    *nout = (int)nb.size();
+    *pool_out = off;
+    if ((int)nb.size() > cap) return fail(c, JANC_EINVAL, "regrid: the new table has %d blocks (capacity %d)", (int)nb.size(), cap);
+    std::copy(nb.begin(), nb.end(), out);
+    return JANC_OK;
+}
+
+janc_status run_regrid_fill(janc_ctx* c, janc_plan* Po, const double* Uo, const double* To,
+                            janc_plan* Pn, double* Un, double* Tn, hipStream_t s) {
+    if (Po->ndom != Pn->ndom) return fail(c, JANC_EINVAL, "regrid fill: plans of different domains");
+    for (int d = 0; d < Po->ndom; ++d) {
+        const DevDomain &A = Po->hdom[d], &B = Pn->hdom[d];
+        if (A.nx0 != B.nx0 || A.ny0 != B.ny0 || A.nlevels != B.nlevels || A.twod != B.twod)
+            return fail(c, JANC_EINVAL, "regrid fill: plans of different domains");
+    }
+    HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    std::map<std::array<int, 6>, long long> old;
+    for (const DevBlock& h : Po->hblk) old[{h.domain, h.level, h.i0, h.j0, h.nx, h.ny}] = h.offset;
+    std::vector<std::vector<RegridFill>> jobs(Pn->maxlev + 1);
+    for (int id = 0; id < (int)Pn->hblk.size(); ++id) {
+        const DevBlock& h = Pn->hblk[id];
+        auto it = old.find({h.domain, h.level, h.i0, h.j0, h.nx, h.ny});
+        const long long src = (it == old.end()) ? -1 : it->second;
+        if (src < 0 && h.level == 0) return fail(c, JANC_EINVAL, "regrid fill: level-0 block %d is not in the old plan", id);
+        jobs[h.level].push_back(RegridFill{id, 0, src});
+    }
+    janc_time tm0{};
+    tm0.cfl = 1.0;
+    StageArgs a = base_args(Pn, &tm0, Un, Tn, nullptr, nullptr, 0);
+    a.Uin = Uo;
+    a.Tin = To;
+    a.Uout = Un;
+    a.Tout = Tn;
+    RegridFill* dj = nullptr;
+    janc_status st = dalloc(c, &dj, Pn->hblk.size());
+    if (st) return st;
+    std::vector<RegridFill> all;
+    for (auto& v : jobs) all.insert(all.end(), v.begin(), v.end());
+    const int nu = n_fields(c->model, c->ns);
+    hipError_t e = hipMemcpyAsync(dj, all.data(), sizeof(RegridFill) * all.size(), hipMemcpyHostToDevice, s);
+    size_t first = 0;
+    for (int l = 0; l <= Pn->maxlev && e == hipSuccess; ++l) {   // coarser layers first
+        e = launch_regrid_fill(a, dj + first, (int)jobs[l].size(), Po->pool, nu, s);
+        first += jobs[l].size();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(dj);
+    if (e != hipSuccess) return hipfail(c, e, "regrid fill");
+    return JANC_OK;
+}
+
 }  // namespace
 
 // =============================================================== C ABI
@@ -1092,6 +1255,21 @@ janc_status janc_plan_create(janc_ctx* c, int nd, const janc_domain* doms, int n
 }
 
 void janc_plan_destroy(janc_plan* p) { plan_free(p); }
+
+janc_status janc_regrid(janc_ctx* c, janc_plan* P, const janc_regrid_params* rp, const double* U,
+                        janc_block* out, int cap, int* nout, long long* pool_out, void* stream) {
+    if (!c || !P || !rp || !U || !nout || !pool_out || cap < 0 || (cap > 0 && !out))
+        return fail(c, JANC_EINVAL, "bad arguments");
+    if (P->ctx != c) return fail(c, JANC_EINVAL, "plan belongs to another context");
+    return run_regrid(c, P, rp, U, out, cap, nout, pool_out, (hipStream_t)stream);
+}
+
+janc_status janc_regrid_fill(janc_ctx* c, janc_plan* Po, const double* Uo, const double* To,
+                             janc_plan* Pn, double* Un, double* Tn, void* stream) {
+    if (!c || !Po || !Pn || !Uo || !To || !Un || !Tn) return fail(c, JANC_EINVAL, "bad arguments");
+    if (Po->ctx != c || Pn->ctx != c) return fail(c, JANC_EINVAL, "plan belongs to another context");
+    return run_regrid_fill(c, Po, Uo, To, Pn, Un, Tn, (hipStream_t)stream);
+}
 
 janc_status janc_plan_stats(const janc_plan* p, long long* out) {
     if (!p || !out) return JANC_EINVAL;

@@ -127,7 +127,16 @@ struct StageArgs {
     const double* Tbase;      // T of the pool (coarser levels' current state)
 };
 
-// Launchers implemented in janc_kernels.hip.
+// Layer update: a candidate subregion (layer-`lev` cells) and a fill job.
+struct RegridCand {
+    int domain, i0, j0, w, h, pad;
+};
+struct RegridFill {
+    int block, pad;           // block of the new plan
+    long long src;            // its cells in the old pool, or -1: inject from the coarser layer
+};
+
+// Launchers implemented in janc_kernels.hip (regrid: janc_regrid.hip).
 hipError_t launch_clear_reduce(const Reduce& r, int which, hipStream_t s);
 hipError_t launch_zero_int(int* p, hipStream_t s);
 hipError_t launch_stage(int model, int ns, int kind_mask, int tile_w, const StageArgs& a,
@@ -138,6 +147,10 @@ hipError_t launch_restrict(int model, int ns, const StageArgs& a, const int* fin
                            int nfine, hipStream_t s);
 hipError_t launch_ring_fill(int model, int ns, const StageArgs& a, const int* ring_blocks,
                             int nring, hipStream_t s);
+hipError_t launch_regrid_flag(const StageArgs& a, const RegridCand* cand, int n, int lev,
+                              int buffer, double thr, int* flags, hipStream_t s);
+hipError_t launch_regrid_fill(const StageArgs& a, const RegridFill* job, int n, long long old_pool,
+                              int nu, hipStream_t s);
 hipError_t launch_prim_to_cons(int model, int ns, const DevMech* mech, double gamma, double R,
                                double Q, long long n, const double* W, double* U, double* T,
                                long long stride_in, long long stride_out, hipStream_t s);

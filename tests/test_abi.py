@@ -50,7 +50,7 @@ def test_struct_layouts_match_c_compiler(tmp_path):
         pytest.skip("no C compiler")
     structs = {"janc_block": L.janc_block, "janc_physics": L.janc_physics,
                "janc_time": L.janc_time, "janc_grid": L.janc_grid, "janc_mech": L.janc_mech,
-               "janc_domain": L.janc_domain}
+               "janc_domain": L.janc_domain, "janc_regrid_params": L.janc_regrid_params}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "janc.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')

@@ -62,7 +62,7 @@ def test_weno5_odd_symmetry(oracle):
 
 # ------------------------------------------------------------------ Sod vs exact Riemann
 def test_sod_normalized_vs_exact(oracle):
-    """BASELINE config 1: normalized Sod, 400 cells, CFL 0.5, t = 0.2."""
+    """Normalized Sod problem: 400 cells, CFL 0.5, t = 0.2."""
     c = sod_case()
     U, T = oracle.case_state(c)
     U, T, t, dts, _ = oracle.step(c, U, T, 2000)
