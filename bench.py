@@ -122,6 +122,7 @@ def main():
     ap.add_argument("--no-per-block", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-crossover", action="store_true")
+    ap.add_argument("--no-regrid", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
@@ -255,6 +256,63 @@ def main():
             f"{rate_x / rate_s:.2f}x the synchronous advance in simulated time per second")
         xplan.close()
 
+    # ------------------------------------------------------------ layer update (regridding)
+    regrid = None
+    if not args.no_regrid:
+        thr, buf, sub, every = 0.05, 4, 8, 40
+        U0, T0, t0 = fresh_state()
+        ctx.step_blocks(plan, tm, U0, T0, 2, t0)
+
+        def one_update():
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            blocks, pool = ctx.regrid(plan, U0, thr, buf, sub)
+            w1 = time.perf_counter()
+            nplan = ctx.plan(domains, blocks, pool, janc.PLAN_DEFAULT)
+            w2 = time.perf_counter()
+            Un, Tn = ctx.regrid_fill(plan, U0, T0, nplan)
+            torch.cuda.synchronize()
+            w3 = time.perf_counter()
+            return (w1 - w0, w2 - w1, w3 - w2), blocks, nplan, Un, Tn
+
+        one_update()[2].close()                    # warm-up
+        reps = [one_update() for _ in range(3)]
+        best = min(reps, key=lambda r: sum(r[0]))
+        for r in reps:
+            if r is not best:
+                r[2].close()
+        (t_flag, t_plan, t_fill), nblocks, nplan, Un, Tn = best
+        total = t_flag + t_plan + t_fill
+        ncells = int(np.sum(nblocks["nx"].astype(np.int64) * nblocks["ny"]))
+        # the step on the updated hierarchy
+        tn = t0.clone()
+        ctx.step_blocks(nplan, tm, Un, Tn, 2, tn)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        rsteps = max(1, args.steps // 4)
+        torch.cuda.synchronize()
+        e0.record()
+        ctx.step_blocks(nplan, tm, Un, Tn, rsteps, tn)
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        r_s = e0.elapsed_time(e1) / 1e3
+        regrid = {"criterion": f"density gradient, threshold {thr}, buffer {buf}, subregion {sub}",
+                  "blocks_before": int(len(case.blocks)), "blocks_after": int(len(nblocks)),
+                  "cells_after": ncells,
+                  "levels_after": [int(x) for x in np.bincount(nblocks["level"])],
+                  "regrid_ms": 1e3 * t_flag, "plan_ms": 1e3 * t_plan, "fill_ms": 1e3 * t_fill,
+                  "update_ms": 1e3 * total,
+                  "every_steps": every,
+                  "amortized_ms_per_step": 1e3 * total / every,
+                  "amortized_fraction_of_step": (1e3 * total / every) / ms_step,
+                  "updated_hierarchy_ms_per_step": 1e3 * r_s / rsteps,
+                  "updated_hierarchy_cell_stage_per_s": ncells * 3 * rsteps / r_s}
+        log(f"[bench] layer update {1e3 * total:.2f} ms (criterion {1e3 * t_flag:.2f}, plan "
+            f"{1e3 * t_plan:.2f}, fill {1e3 * t_fill:.2f}); {len(case.blocks)} -> {len(nblocks)} "
+            f"blocks, {ncells} cells; every {every} steps: {1e3 * total / every:.3f} ms/step; "
+            f"updated hierarchy {1e3 * r_s / rsteps:.3f} ms/step")
+        nplan.close()
+
     # ------------------------------------------------------------ adjoint / forward cost
     adjoint = None
     if not args.no_adjoint:
@@ -349,6 +407,7 @@ def main():
                        "restriction": float(np.mean(restr_ms)), "ring": float(np.mean(ring_ms))},
         "per_block": per_block,
         "crossover": crossover,
+        "regrid": regrid,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
         "context": "paper (A100, real H2-O2 mechanism, 2.76 M cells incl. invalid blocks): "
