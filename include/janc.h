@@ -102,14 +102,21 @@ typedef struct {
  *                     dt (the order of the paper's advance_one_step listing);
  *   JANC_SPLIT_STRANG point-implicit step over dt/2, three RK stages over dt,
  *                     point-implicit step over dt/2 (Strang splitting, Sec. 4.2).
- * Any other value, and JANC_SPLIT_STRANG with a model without chemistry, is
- * JANC_EINVAL. */
+ * jac selects the Jacobian of the point-implicit step (Eq. 4.12):
+ *   JANC_JAC_FROZEN_T derivatives with respect to rho Y_1 .. rho Y_{Ns-1} with T,
+ *                     rho, E and momentum held constant (as Sec. 4.2 states);
+ *   JANC_JAC_FULL     the same variables, with T following the composition at
+ *                     fixed rho and internal energy: J + (dS/dT)(dT/d rho Y)^T,
+ *                     dT/d rho Y_m = -(e_m - e_Ns) / (rho c_v).
+ * Any other value of split or jac, and JANC_SPLIT_STRANG or JANC_JAC_FULL with a
+ * model without chemistry, is JANC_EINVAL. */
 enum { JANC_SPLIT_LIE = 0, JANC_SPLIT_STRANG = 1 };
+enum { JANC_JAC_FROZEN_T = 0, JANC_JAC_FULL = 1 };
 
 typedef struct {
     double cfl, dt_fixed, t_end;
     int split;
-    int pad_;
+    int jac;
 } janc_time;
 
 typedef struct janc_ctx janc_ctx;

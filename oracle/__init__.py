@@ -38,7 +38,7 @@ class OGrid(C.Structure):
 
 
 class OTime(C.Structure):
-    _fields_ = [("cfl", D), ("dt_fixed", D), ("t_end", D), ("split", I), ("pad", I)]
+    _fields_ = [("cfl", D), ("dt_fixed", D), ("t_end", D), ("split", I), ("jac", I)]
 
 
 class ODomain(C.Structure):
@@ -178,18 +178,20 @@ def rhs(case, U, T):
 
 
 def step(case, U, T, nsteps, t=0.0, cfl=None, dt_fixed=None, t_end=None, check=True,
-         strang=False):
+         strang=False, full_jacobian=False):
     """Advance nsteps; returns (U, T, t, dt_log, status).
 
     strang=False: chemistry over dt after the RK stages (Lie); True: over dt/2 before
-    and after them (Strang splitting, Sec. 4.2)."""
+    and after them (Strang splitting, Sec. 4.2). full_jacobian: the point-implicit
+    Jacobian lets T follow the composition at fixed rho and e (species + T variant)."""
     U = _f64(U).copy()
     T = _f64(T).copy()
     mv = _MechView(case.mech)
     ph, g = _phys(case), _grid(case)
     tm = OTime(case.cfl if cfl is None else cfl,
                case.dt_fixed if dt_fixed is None else dt_fixed,
-               case.t_end if t_end is None else t_end, 1 if strang else 0, 0)
+               case.t_end if t_end is None else t_end, 1 if strang else 0,
+               1 if full_jacobian else 0)
     bp = _bc_prim(case.nU, case.bc, case.bc_prim)
     tt = D(t)
     dts = np.zeros(max(nsteps, 1))
@@ -240,7 +242,7 @@ def block_state(bcase):
 
 
 def step_blocks(bcase, U, T, nsteps, t=None, cfl=None, dt_fixed=None, t_end=None, check=True,
-                crossover=False, strang=False):
+                crossover=False, strang=False, full_jacobian=False):
     """Advance a block table nsteps; returns (U, T, t[ndom], dt_log[nsteps, ndom], status).
 
     crossover=False: synchronous advance (paper Fig. 2b); True: crossover advance (Fig. 2a,
@@ -257,7 +259,8 @@ def step_blocks(bcase, U, T, nsteps, t=None, cfl=None, dt_fixed=None, t_end=None
     blocks = np.ascontiguousarray(bcase.blocks)
     tm = OTime(bcase.cfl if cfl is None else cfl,
                bcase.dt_fixed if dt_fixed is None else dt_fixed,
-               bcase.t_end if t_end is None else t_end, 1 if strang else 0, 0)
+               bcase.t_end if t_end is None else t_end, 1 if strang else 0,
+               1 if full_jacobian else 0)
     tt = np.zeros(nd) if t is None else _f64(t).copy()
     dts = np.zeros((max(nsteps, 1), nd))
     st = lib().oracle_step_blocks(I(bcase.model), mv.ptr, I(nd), doms, _p(bp), I(len(blocks)),
@@ -373,6 +376,17 @@ def production(mech, rho, T, rhoY, jacobian=False):
     lib().oracle_production(mv.ptr, D(rho), D(T), _p(rhoY), _p(w),
                             _p(J) if jacobian else None)
     return (w, J) if jacobian else w
+
+
+def full_jacobian(mech, rho, e, T, rhoY):
+    """dS/d(rho Y_1..rho Y_{Ns-1}) with T following the composition at fixed rho and e."""
+    mv = _MechView(mech)
+    rhoY = _f64(rhoY).copy()
+    nt = mech.ns - 1
+    J = np.zeros((nt, nt))
+    st = lib().oracle_full_jacobian(mv.ptr, D(rho), D(e), D(T), _p(rhoY), _p(J))
+    _check(st, "full_jacobian")
+    return J
 
 
 def point_implicit(mech, rho, T, rhoY, dt):

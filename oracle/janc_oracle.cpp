@@ -47,6 +47,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 #include <algorithm>
 #ifdef _OPENMP
@@ -109,6 +110,7 @@ struct MechData {
 template <class S> struct Phys {
     int model = 0;
     int nU = 0;
+    int full_jac = 0;   // point-implicit Jacobian with T following the composition
     S gamma, R, Q, Ea, k;
     const MechData* mech = nullptr;
 };
@@ -386,13 +388,15 @@ template <class S> int gauss_solve(int n, S* A, S* b) {
     return ST_OK;
 }
 
-// Point-implicit update of rho Y_1..rho Y_{Ns-1} over dt (Eq. 4.12-4.13).
+// Point-implicit update of rho Y_1..rho Y_{Ns-1} over dt (Eq. 4.12-4.13); Jext, when
+// given, replaces the Jacobian at frozen T.
 template <class S> int point_implicit(const MechData& m, const S& rho, const S& T, S* rhoY,
-                                      const S& dt) {
+                                      const S& dt, const S* Jext = nullptr) {
     const int nt = m.ns - 1;
     S wdot[32];
     std::vector<S> J(nt * nt), A(nt * nt);
     production(m, rho, T, rhoY, wdot, J.data());
+    if (Jext) std::copy(Jext, Jext + nt * nt, J.begin());
     S rhs[32];
     for (int k = 0; k < nt; ++k) {
         for (int q = 0; q < nt; ++q) A[k * nt + q] = (k == q ? 1.0 : 0.0) - dt * J[k * nt + q];
@@ -524,10 +528,51 @@ template <class S> int cell_temperature(const Phys<S>& ph, const S* U, const S& 
     return ST_OK;
 }
 
+// Jacobian of the production rates S(rho Y_1..rho Y_{Ns-1}) when T follows the
+// composition at fixed rho and internal energy e (the "full" variant: species and T).
+// Column m is the tangent of S(rhoY, T(rhoY)) along rho Y_m: T comes from Newton on
+// dual numbers started at the converged T, so its tangent is the implicit-function
+// derivative -(de/d rhoY_m) / (de/dT).
+int full_jacobian(const MechData& m, double rho, double e, double T, const double* rhoY,
+                  double* J) {
+    const int nt = m.ns - 1;
+    for (int mm = 0; mm < nt; ++mm) {
+        Dual ry[32], Y[32], w[32];
+        Dual sum = 0.0;
+        for (int k = 0; k < nt; ++k) {
+            ry[k] = Dual(rhoY[k], k == mm ? 1.0 : 0.0);
+            Y[k] = ry[k] / Dual(rho);
+            sum = sum + Y[k];
+        }
+        Y[nt] = 1.0 - sum;
+        Dual Td(T, 0.0);
+        int st = newton_T(m, Y, Dual(e), Td);
+        if (st) return st;
+        production(m, Dual(rho), Td, ry, w, (Dual*)nullptr);
+        for (int k = 0; k < nt; ++k) J[k * nt + mm] = w[k].d;
+    }
+    return ST_OK;
+}
+
 // Chemistry step of one cell (DETAILED), then Newton for the new T.
 template <class S> int cell_chemistry(const Phys<S>& ph, S* U, S& T, const S& dt) {
     const MechData& m = *ph.mech;
-    int st = point_implicit(m, U[0], T, &U[4], dt);
+    int st;
+    if constexpr (std::is_same<S, double>::value) {
+        if (ph.full_jac) {
+            const int nt = m.ns - 1;
+            std::vector<double> Jf((size_t)nt * nt);
+            const double u = U[1] / U[0], v = U[2] / U[0];
+            const double e = U[3] / U[0] - 0.5 * (u * u + v * v);
+            st = full_jacobian(m, U[0], e, T, &U[4], Jf.data());
+            if (!st) st = point_implicit(m, U[0], T, &U[4], dt, Jf.data());
+        } else {
+            st = point_implicit(m, U[0], T, &U[4], dt);
+        }
+    } else {
+        if (ph.full_jac) return ST_EINVAL;
+        st = point_implicit(m, U[0], T, &U[4], dt);
+    }
     if (st) return st;
     S Tn = 0.0;
     st = cell_temperature(ph, U, T, Tn);
@@ -1529,7 +1574,7 @@ struct OMech {
 };
 struct OPhys { int model; double gamma, R, Q, Ea, k; };
 struct OGrid { int nx, ny; double dx, dy; int bc[4]; };
-struct OTime { double cfl, dt_fixed, t_end; int split, pad; };
+struct OTime { double cfl, dt_fixed, t_end; int split, jac; };
 
 MechData mech_from(const OMech* m) {
     MechData d;
@@ -1707,6 +1752,13 @@ int oracle_point_implicit(const OMech* m, double rho, double T, double* rhoY, do
     return point_implicit(md, rho, T, rhoY, dt);
 }
 
+// The species + T Jacobian (see full_jacobian) at (rho, e, T, rhoY); J [Ns-1][Ns-1].
+int oracle_full_jacobian(const OMech* m, double rho, double e, double T, const double* rhoY,
+                         double* J) {
+    MechData md = mech_from(m);
+    return full_jacobian(md, rho, e, T, rhoY, J);
+}
+
 // L(U) on a uniform grid (one evaluation of the semi-discrete right-hand side).
 int oracle_rhs(const OGrid* g, const OPhys* p, const OMech* m, const double* bc_prim,
                const double* U, const double* T, double* L) {
@@ -1734,6 +1786,8 @@ int oracle_step(const OGrid* g, const OPhys* p, const OMech* m, const double* bc
     BCStates<double> bcs;
     if (bc_states_from(ph, g, bc_prim, bcs)) return ST_EINVAL;
     if (tm->split != 0 && (tm->split != 1 || ph.model != MODEL_DETAILED)) return ST_EINVAL;
+    if (tm->jac != 0 && (tm->jac != 1 || ph.model != MODEL_DETAILED)) return ST_EINVAL;
+    ph.full_jac = tm->jac;
     TimeCfg tc{tm->cfl, tm->dt_fixed, tm->t_end, tm->split};
     long long n = (long long)gc.nx * gc.ny;
     std::vector<double> Ua, Ta(T, T + n);
@@ -1759,6 +1813,7 @@ int oracle_step_blocks(int model, const OMech* m, int ndom, const ODomain* doms,
                        const BlockRec* blocks, long long pool, const OTime* tm, double* U,
                        double* T, int nsteps, double* t_dom, double* dt_log, int crossover) {
     if (tm->split != 0 && (tm->split != 1 || model != MODEL_DETAILED)) return ST_EINVAL;
+    if (tm->jac != 0 && (tm->jac != 1 || model != MODEL_DETAILED)) return ST_EINVAL;
     MechData md = mech_from(m);
     BlockSet B;
     B.pool = pool;
@@ -1775,6 +1830,7 @@ int oracle_step_blocks(int model, const OMech* m, int ndom, const ODomain* doms,
         B.dom.push_back(r);
         OPhys op{model, r.gamma, r.R, r.Q, r.Ea, r.k};
         phys[d] = phys_from<double>(&op, m ? &md : nullptr);
+        phys[d].full_jac = tm->jac;
         for (int s = 0; s < 4; ++s) {
             bcU[d * 4 + s].assign(B.nU, 0.0);
             if (r.bc[s] == BC_DIRICHLET) {

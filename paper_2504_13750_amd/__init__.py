@@ -21,6 +21,7 @@ CPG, ONESTEP, DETAILED = 0, 1, 2
 BC_PERIODIC, BC_ZEROGRAD, BC_SLIPWALL, BC_DIRICHLET = 0, 1, 2, 3
 PLAN_DEFAULT, PLAN_PER_BLOCK, PLAN_NO_GRAPH, PLAN_CROSSOVER = 0, 1, 2, 4
 SPLIT_LIE, SPLIT_STRANG = 0, 1
+JAC_FROZEN_T, JAC_FULL = 0, 1
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONFINITE", -5: "ENEWTON",
           -6: "ENEGATIVE"}
 
@@ -82,10 +83,11 @@ def make_physics(gamma=1.4, R=1.0, Q=0.0, Ea=0.0, k=0.0):
     return L.janc_physics(float(gamma), float(R), float(Q), float(Ea), float(k))
 
 
-def make_time(cfl=0.5, dt_fixed=0.0, t_end=0.0, split=0):
+def make_time(cfl=0.5, dt_fixed=0.0, t_end=0.0, split=0, jac=0):
     """split: SPLIT_LIE (chemistry over dt after the RK stages) or SPLIT_STRANG
-    (chemistry over dt/2 before and after them)."""
-    return L.janc_time(float(cfl), float(dt_fixed), float(t_end), int(split), 0)
+    (chemistry over dt/2 before and after them); jac: JAC_FROZEN_T or JAC_FULL
+    (point-implicit Jacobian with T following the composition)."""
+    return L.janc_time(float(cfl), float(dt_fixed), float(t_end), int(split), int(jac))
 
 
 def grid_of(case):

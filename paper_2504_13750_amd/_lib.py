@@ -31,7 +31,7 @@ class janc_grid(C.Structure):
 
 
 class janc_time(C.Structure):
-    _fields_ = [("cfl", D), ("dt_fixed", D), ("t_end", D), ("split", C.c_int), ("pad_", C.c_int)]
+    _fields_ = [("cfl", D), ("dt_fixed", D), ("t_end", D), ("split", C.c_int), ("jac", C.c_int)]
 
 
 class janc_domain(C.Structure):

@@ -46,10 +46,11 @@ struct GraphKey {
     const double *U, *T, *t, *dt_log;
     int cap;
     double cfl, dt_fixed, t_end;
-    int split;
+    int split, jac;
     bool operator==(const GraphKey& o) const {
         return U == o.U && T == o.T && t == o.t && dt_log == o.dt_log && cap == o.cap &&
-               cfl == o.cfl && dt_fixed == o.dt_fixed && t_end == o.t_end && split == o.split;
+               cfl == o.cfl && dt_fixed == o.dt_fixed && t_end == o.t_end && split == o.split &&
+               jac == o.jac;
     }
 };
 
@@ -118,6 +119,10 @@ janc_status check_time(janc_ctx* c, const janc_time* tm) {
         return fail(c, JANC_EINVAL, "split must be JANC_SPLIT_LIE or JANC_SPLIT_STRANG");
     if (tm->split == JANC_SPLIT_STRANG && c->model != DETAILED)
         return fail(c, JANC_EINVAL, "Strang splitting needs a model with chemistry (detailed)");
+    if (tm->jac != JANC_JAC_FROZEN_T && tm->jac != JANC_JAC_FULL)
+        return fail(c, JANC_EINVAL, "jac must be JANC_JAC_FROZEN_T or JANC_JAC_FULL");
+    if (tm->jac == JANC_JAC_FULL && c->model != DETAILED)
+        return fail(c, JANC_EINVAL, "the species + T Jacobian needs a model with chemistry (detailed)");
     return JANC_OK;
 }
 
@@ -501,6 +506,7 @@ StageArgs base_args(janc_plan* P, const janc_time* tm, double* U, double* T, dou
     a.dt_log_cap = cap;
     a.tm = TimeArgs{tm->cfl, tm->dt_fixed, tm->t_end};
     a.strang = (tm->split == JANC_SPLIT_STRANG && P->ctx->model == DETAILED) ? 1 : 0;
+    a.full_jac = (tm->jac == JANC_JAC_FULL && P->ctx->model == DETAILED) ? 1 : 0;
     a.status = P->ctx->dstatus;
     if (P->flags & JANC_PLAN_CROSSOVER) {
         a.cross = 1;
@@ -694,7 +700,7 @@ janc_status run_steps(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U,
         for (int n = 0; n < nsteps; ++n) HIPCHK(c, enqueue_step(P, base, U, T, s), "step launch");
         return JANC_OK;
     }
-    const GraphKey key{U, T, t, dt_log, nsteps, tm->cfl, tm->dt_fixed, tm->t_end, tm->split};
+    const GraphKey key{U, T, t, dt_log, nsteps, tm->cfl, tm->dt_fixed, tm->t_end, tm->split, tm->jac};
     if (!P->have_graph || !(P->gkey == key)) {
         drop_graph(P);
         hipStream_t cs;

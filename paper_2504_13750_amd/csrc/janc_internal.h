@@ -69,13 +69,13 @@ struct DevMech {
     double tb[MAXR][MAXS];
 };
 
-// Reduction slots (three rotating buffers of `stride` 64-bit words): per
-// (domain, level) unit the maxima of |u|+c and |v|+c (Eq. 4.11), per domain
-// the CFL bound max((|u|+c)/dx + (|v|+c)/dy). Non-negative doubles are stored
-// by bit pattern, so an unsigned integer max is the floating-point max.
-// Reduction slot buffers per slot set: buffers 0-2 rotate through the RK stages
-// (stage s reads s - 1, writes s mod 3, clears s + 1 mod 3); buffer 3 carries the
-// maxima of the first half chemistry step to stage 1 under Strang splitting.
+// Reduction slots (buffers of `stride` 64-bit words): per (domain, level) unit
+// the maxima of |u|+c and |v|+c (Eq. 4.11), per domain the CFL bound
+// max((|u|+c)/dx + (|v|+c)/dy). Non-negative doubles are stored by bit pattern,
+// so an unsigned integer max is the floating-point max. Buffers 0-2 rotate
+// through the RK stages (stage s reads s - 1, writes s mod 3, clears s + 1 mod 3);
+// buffer 3 carries the maxima of the first half chemistry step to stage 1 under
+// Strang splitting.
 constexpr int RED_BUFS = 4;
 
 struct Reduce {
@@ -117,6 +117,7 @@ struct StageArgs {
     unsigned* status;
     int strang;               // Strang splitting: chemistry over dt/2 before and after the stages
     int chem_phase;           // chemistry launch: 0 whole dt, 1 first half, 2 second half
+    int full_jac;             // point-implicit Jacobian with T following the composition
     // crossover advance (per-level launches, dt_l = dt_0 / 2^l); all zero otherwise
     int cross;
     int xfirst;               // first launch of the step: computes dt_0

@@ -380,7 +380,7 @@ __global__ __launch_bounds__(WG) void init_kernel(StageArgs a) {
 // LDS hold X, the species Gibbs terms and the derivative row dq/dX of the
 // current reaction (indexed by wave-uniform species numbers); the (Ns-1)^2
 // Jacobian, the production rates and the LU factorization live in registers.
-template <int NS>
+template <int NS, bool FULLJ>
 __device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, double* dqs,
                                           double rho, double T, const double (&rY)[NS - 1],
                                           double dt, double (&w)[NS - 1], unsigned& st) {
@@ -406,6 +406,25 @@ __device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, dou
         gts[j * WG + tid] = a[0] * (1.0 - lnT) -
                 T * (0.5 * a[1] + T * (a[2] * (1.0 / 6.0) + T * (a[3] * (1.0 / 12.0) + T * (a[4] * 0.05)))) +
                 a[5] * invT - a[6];
+    }
+    // species + T Jacobian: T follows the composition at fixed rho and e, so
+    // J += (dS/dT) (dT/d rho Y)^T with dT/d rho Y_m = -(e_m - e_last) / (rho c_v);
+    // hm1[j] = h_j/(R_u T) - 1 = e_j / (R_u T) per mole, cvs = rho c_v / R_u
+    double hm1[NS], dSdT[NT];
+    double cvs = 0.0;
+    if constexpr (FULLJ) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const bool hi = m->two_range && T >= m->tmid[j];
+            double a[7];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) a[q] = hi ? m->nasa_hi[j][q] : m->nasa[j][q];
+            hm1[j] = a[0] + T * (0.5 * a[1] + T * (a[2] * (1.0 / 3.0) + T * (0.25 * a[3] + T * (0.2 * a[4])))) +
+                     a[5] * invT - 1.0;
+            cvs += Xs[j * WG + tid] * (a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4]))) - 1.0);
+        }
+#pragma unroll
+        for (int k = 0; k < NT; ++k) dSdT[k] = 0.0;
     }
     double J[NT][NT];
 #pragma unroll
@@ -442,6 +461,20 @@ __device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, dou
         const double q = ctb * net;
 #pragma unroll
         for (int k = 0; k < NT; ++k) w[k] += m->Mdnu[i][k] * q;
+        if constexpr (FULLJ) {
+            // d ln kf/dT = (b + Ea/(R T))/T; d ln kb/dT = d ln kf/dT - sum_j dnu_j (H_j - 1)/T
+            const double dlf = (m->b[i] + m->EaR[i] * invT) * invT;
+            double dlb = dlf;
+            if (m->rev[i]) {
+                double sh = 0.0;
+#pragma unroll
+                for (int j = 0; j < NS; ++j) sh += (double)m->dnu[i][j] * hm1[j];
+                dlb = dlf - sh * invT;
+            }
+            const double dqT = ctb * (Rf * dlf - Rb * dlb);
+#pragma unroll
+            for (int k = 0; k < NT; ++k) dSdT[k] += m->Mdnu[i][k] * dqT;
+        }
         // dq/dX_j into LDS (padding slot NS absorbs the entries of missing molecules)
 #pragma unroll
         for (int j = 0; j <= NS; ++j) dqs[j * WG + tid] = (tbr && j < NS) ? m->tb[i][j] * net : 0.0;
@@ -464,6 +497,15 @@ __device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, dou
 #pragma unroll
                 for (int mm = 0; mm < NT; ++mm) J[k][mm] += ck * Dm[mm];
             }
+        }
+    }
+    if constexpr (FULLJ) {
+        const double ilast = hm1[NT] * m->invM[NT];
+#pragma unroll
+        for (int mm = 0; mm < NT; ++mm) {
+            const double dTm = -T * (hm1[mm] * m->invM[mm] - ilast) / cvs;
+#pragma unroll
+            for (int k = 0; k < NT; ++k) J[k][mm] += dSdT[k] * dTm;
         }
     }
     // (I - dt J) dU = dt w, Gaussian elimination without pivoting, in place;
@@ -499,7 +541,7 @@ __device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, dou
 #ifndef CHEM_WAVES
 #define CHEM_WAVES 1
 #endif
-template <int NS>
+template <int NS, bool FULLJ>
 __global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
     constexpr int NU = NS + 3;
     __shared__ double Xs[(NS + 1) * WG];
@@ -546,7 +588,7 @@ __global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
             for (int k = 0; k < NS - 1; ++k) rY[k] = a.Uout[(size_t)(4 + k) * a.pool + r.c];
             T = a.Tout[r.c];
         }
-        chem_cell<NS>(mech, Xs, gts, dqs, rho, T, rY, dt, dY, st);
+        chem_cell<NS, FULLJ>(mech, Xs, gts, dqs, rho, T, rY, dt, dY, st);
     }
     if (r.own) {
         double u[NU];
@@ -767,8 +809,10 @@ hipError_t launch_init(int model, int ns, int tile_w, const StageArgs& a, hipStr
 hipError_t launch_chem(int model, int ns, int tile_w, const StageArgs& a, hipStream_t s) {
     (void)tile_w;
     if (model != DETAILED || a.ntiles <= 0) return hipSuccess;
-    if (ns == 9) chem_kernel<9><<<a.ntiles, WG, 0, s>>>(a);
-    else if (ns == 2) chem_kernel<2><<<a.ntiles, WG, 0, s>>>(a);
+    if (ns == 9 && a.full_jac) chem_kernel<9, true><<<a.ntiles, WG, 0, s>>>(a);
+    else if (ns == 9) chem_kernel<9, false><<<a.ntiles, WG, 0, s>>>(a);
+    else if (ns == 2 && a.full_jac) chem_kernel<2, true><<<a.ntiles, WG, 0, s>>>(a);
+    else if (ns == 2) chem_kernel<2, false><<<a.ntiles, WG, 0, s>>>(a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -26,10 +26,11 @@ def context_for(case):
     return janc.Context(case.model, case.mech)
 
 
-def run_uniform(case, nsteps, ctx=None, dt_fixed=None, t_end=None, cfl=None, W=None, split=0):
+def run_uniform(case, nsteps, ctx=None, dt_fixed=None, t_end=None, cfl=None, W=None, split=0,
+                jac=0):
     """init_state + janc_step on the GPU; returns numpy (U, T, t, dt_log)."""
     print(f"[gpu] janc_step {case.name} model={case.model} {case.nx}x{case.ny} nsteps={nsteps} "
-          f"split={split}", flush=True)
+          f"split={split} jac={jac}", flush=True)
     torch, dev = torch_dev()
     own = ctx is None
     ctx = ctx or context_for(case)
@@ -46,6 +47,7 @@ def run_uniform(case, nsteps, ctx=None, dt_fixed=None, t_end=None, cfl=None, W=N
     if cfl is not None:
         kw["cfl"] = cfl
     kw["split"] = split
+    kw["jac"] = jac
     ctx.step(janc.grid_of(case), phys, janc.time_of(case, **kw), U, T, nsteps, t, dts)
     ctx.sync_status()
     out = (U.cpu().numpy(), T.cpu().numpy(), t.item(), dts.cpu().numpy()[:nsteps])
@@ -69,9 +71,9 @@ def init_blocks(ctx, bcase):
     return U, T
 
 
-def run_blocks(bcase, nsteps, ctx=None, flags=0, tile=0, keep=False, split=0):
+def run_blocks(bcase, nsteps, ctx=None, flags=0, tile=0, keep=False, split=0, jac=0):
     print(f"[gpu] janc_step_blocks {bcase.name} blocks={len(bcase.blocks)} "
-          f"pool={bcase.pool_cells} nsteps={nsteps} flags={flags} tile={tile} split={split}",
+          f"pool={bcase.pool_cells} nsteps={nsteps} flags={flags} tile={tile} split={split} jac={jac}",
           flush=True)
     torch, dev = torch_dev()
     own = ctx is None
@@ -81,7 +83,7 @@ def run_blocks(bcase, nsteps, ctx=None, flags=0, tile=0, keep=False, split=0):
         plan.set_tile(tile)
     U, T = init_blocks(ctx, bcase)
     t = torch.zeros(len(bcase.domains), dtype=torch.float64, device=dev)
-    ctx.step_blocks(plan, janc.time_of(bcase, split=split), U, T, nsteps, t)
+    ctx.step_blocks(plan, janc.time_of(bcase, split=split, jac=jac), U, T, nsteps, t)
     ctx.sync_status()
     out = (U.cpu().numpy(), T.cpu().numpy(), t.cpu().numpy())
     plan.close()

@@ -31,7 +31,8 @@ def _cmp_blocks(bcase, nsteps, tol=TOL, crossover=False, **kw):
     Ug, Tg, tg = run_blocks(bcase, nsteps, **kw)
     Uo, To = oracle.block_state(bcase)
     Uo, To, to, _, _ = oracle.step_blocks(bcase, Uo, To, nsteps, crossover=crossover,
-                                          strang=kw.get("split", 0) == 1)
+                                          strang=kw.get("split", 0) == 1,
+                                          full_jacobian=kw.get("jac", 0) == 1)
     valid = np.zeros(bcase.pool_cells, bool)
     for b in bcase.blocks[bcase.blocks["valid"] != 0]:
         valid[b["offset"]:b["offset"] + b["nx"] * b["ny"]] = True
@@ -194,3 +195,13 @@ def test_strang_launch_forms_agree_bitwise():
     Uc, Tc, tc = run_blocks(bc, 3, split=janc.SPLIT_STRANG, flags=janc.PLAN_PER_BLOCK)
     assert np.array_equal(Ua, Ub) and np.array_equal(Ta, Tb) and np.array_equal(ta, tb)
     assert np.array_equal(Ua, Uc) and np.array_equal(Ta, Tc) and np.array_equal(ta, tc)
+
+
+# ------------------------------------------------------------------ species + T Jacobian
+def test_full_jacobian_amr_detailed_vs_oracle():
+    _cmp_blocks(_small_detailed_amr(), 3, jac=janc.JAC_FULL)
+
+
+def test_full_jacobian_strang_crossover_vs_oracle():
+    _cmp_blocks(_small_detailed_amr(), 2, crossover=True, split=janc.SPLIT_STRANG,
+                jac=janc.JAC_FULL)

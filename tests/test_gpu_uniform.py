@@ -25,6 +25,7 @@ def _compare(case, nsteps, tol=TOL, **kw):
     Uo, To = oracle.case_state(case)
     okw = {k: v for k, v in kw.items() if k in ("dt_fixed", "t_end", "cfl")}
     okw["strang"] = kw.get("split", 0) == 1
+    okw["full_jacobian"] = kw.get("jac", 0) == 1
     Uo, To, to, do, _ = oracle.step(case, Uo, To, nsteps, **okw)
     e = rel_err(Ug, Uo)
     eT = rel_err(Tg[None], To[None])[0]
@@ -168,4 +169,35 @@ def test_strang_rejected_without_chemistry():
     c = detonation_tube_case(nx=16, ny=8, seed=3)
     with pytest.raises(janc.JancError) as ei:
         run_uniform(c, 1, split=1)
+    assert ei.value.code == -1
+
+
+def test_detailed_front_full_jacobian():
+    c = detailed_front_case(nx=48, ny=40)
+    _compare(c, 4, jac=1)
+
+
+def test_detailed_front_full_jacobian_two_range_strang():
+    from cases import synthetic_mechanism, two_range_mechanism
+    c = detailed_front_case(nx=48, ny=40, mech=two_range_mechanism(synthetic_mechanism()))
+    _compare(c, 4, jac=1, split=1)
+
+
+def test_chemkin_loaded_mechanism_drives_the_library():
+    """A mechanism written to chemkin text and read back (two NASA-7 ranges) runs the
+    9-species front like the oracle does with the same loaded mechanism."""
+    from paper_2504_13750_amd import chemkin
+    from cases import synthetic_mechanism, two_range_mechanism
+    m0 = two_range_mechanism(synthetic_mechanism())
+    m = chemkin.parse(chemkin.write(m0, atomic_weights={"A": 2.0, "B": 16.0, "C": 14.0}),
+                      complement="C2")
+    c = detailed_front_case(nx=48, ny=40, mech=m)
+    _compare(c, 4)
+
+
+def test_full_jacobian_rejected_without_chemistry():
+    import paper_2504_13750_amd as janc
+    c = detonation_tube_case(nx=16, ny=8, seed=3)
+    with pytest.raises(janc.JancError) as ei:
+        run_uniform(c, 1, jac=1)
     assert ei.value.code == -1
