@@ -619,7 +619,8 @@ __global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
 // Four-to-one restriction (Sec. 3.1.4 coarsening): each coarse cell under a
 // valid block of this level becomes the mean of its four children (ring
 // children count with their effective value, the coarse cell itself); T is
-// re-solved; the coarse cell enters the maxima of the next step.
+// re-solved; the coarse cell enters the maxima of the next step. Workgroup
+// (b, y) takes coarse cells y*WG, y*WG + gridDim.y*WG, ... of fine block b.
 template <int M, int NU>
 __global__ __launch_bounds__(WG) void restrict_kernel(StageArgs a, const int* fine_blocks) {
     __shared__ double scratch[16];
@@ -627,12 +628,12 @@ __global__ __launch_bounds__(WG) void restrict_kernel(StageArgs a, const int* fi
     CDom& D = cdom(a.dom, B.domain);
     const int lev = B.level;
     const double dt = a.dt[B.domain];
-    if (!(dt > 0.0)) return;
     const int cw = B.nx / 2, ch = B.ny / 2;
+    if (!(dt > 0.0) || (int)blockIdx.y * WG >= cw * ch) return;
     const int cslot = D.slot0 + lev - 1;
     const double idx = (double)(1 << (lev - 1)) / D.dx0, idy = (double)(1 << (lev - 1)) / D.dy0;
     double sx = 0.0, sy = 0.0, sc = 0.0;
-    for (int cc = threadIdx.x; cc < cw * ch; cc += WG) {
+    for (int cc = blockIdx.y * WG + threadIdx.x; cc < cw * ch; cc += gridDim.y * WG) {
         const int cj = cc / cw, ci = cc - cj * cw;
         unsigned fl = 0u;
         const long long cpar = resolve(a, D, lev - 1, (B.i0 >> 1) + ci, (B.j0 >> 1) + cj, fl);
@@ -669,13 +670,27 @@ __global__ __launch_bounds__(WG) void restrict_kernel(StageArgs a, const int* fi
 }
 
 // Ring cells take the injection (one-to-four) of the coarser level after restriction.
+// Only the 3-cell bands along the four sides can hold ring cells: workgroup (b, y)
+// walks the band cells y*WG, y*WG + gridDim.y*WG, ... of block b (W, E, S, N bands;
+// a corner cell lies in two bands and is written twice with the same value).
 template <int NU>
 __global__ __launch_bounds__(WG) void ring_fill_kernel(StageArgs a, const int* ring_blocks) {
     const DevBlock B = a.blk[ring_blocks[blockIdx.x]];
     CDom& D = cdom(a.dom, B.domain);
-    if (!(a.dt[B.domain] > 0.0)) return;
-    for (int q = threadIdx.x; q < B.nx * B.ny; q += WG) {
-        const int lj = q / B.nx, li = q - lj * B.nx;
+    const int nband = 6 * B.ny + 6 * B.nx;
+    if (!(a.dt[B.domain] > 0.0) || (int)blockIdx.y * WG >= nband) return;
+    for (int q = blockIdx.y * WG + threadIdx.x; q < nband; q += gridDim.y * WG) {
+        int li, lj;
+        if (q < 6 * B.ny) {
+            const int r = (q < 3 * B.ny) ? q : q - 3 * B.ny;
+            lj = r / 3;
+            li = (q < 3 * B.ny) ? r - 3 * lj : B.nx - 3 + (r - 3 * lj);
+        } else {
+            const int h = q - 6 * B.ny, r = (h < 3 * B.nx) ? h : h - 3 * B.nx;
+            const int row = r / B.nx;
+            li = r - row * B.nx;
+            lj = (h < 3 * B.nx) ? row : B.ny - 3 + row;
+        }
         if (!ring_at(B, li, lj)) continue;
         unsigned fl = 0u;
         const long long s = resolve(a, D, B.level - 1, (B.i0 + li) >> 1, (B.j0 + lj) >> 1, fl);
@@ -817,13 +832,18 @@ hipError_t launch_chem(int model, int ns, int tile_w, const StageArgs& a, hipStr
     return hipGetLastError();
 }
 
+// Workgroups per block of the restriction and ring-fill launches (a 64 x 64 fine
+// block has 1024 coarse cells and 768 band cells: four workgroups of 256 threads).
+constexpr int RESTRICT_SPLIT = 4;
+
 hipError_t launch_restrict(int model, int ns, const StageArgs& a, const int* fine_blocks, int nfine,
                            hipStream_t s) {
     if (nfine <= 0) return hipSuccess;
-    if (model == CPG) restrict_kernel<CPG, 4><<<nfine, WG, 0, s>>>(a, fine_blocks);
-    else if (model == ONESTEP) restrict_kernel<ONESTEP, 5><<<nfine, WG, 0, s>>>(a, fine_blocks);
-    else if (ns == 9) restrict_kernel<DETAILED, 12><<<nfine, WG, 0, s>>>(a, fine_blocks);
-    else if (ns == 2) restrict_kernel<DETAILED, 5><<<nfine, WG, 0, s>>>(a, fine_blocks);
+    const dim3 grid(nfine, RESTRICT_SPLIT);
+    if (model == CPG) restrict_kernel<CPG, 4><<<grid, WG, 0, s>>>(a, fine_blocks);
+    else if (model == ONESTEP) restrict_kernel<ONESTEP, 5><<<grid, WG, 0, s>>>(a, fine_blocks);
+    else if (ns == 9) restrict_kernel<DETAILED, 12><<<grid, WG, 0, s>>>(a, fine_blocks);
+    else if (ns == 2) restrict_kernel<DETAILED, 5><<<grid, WG, 0, s>>>(a, fine_blocks);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -832,9 +852,10 @@ hipError_t launch_ring_fill(int model, int ns, const StageArgs& a, const int* ri
                             hipStream_t s) {
     if (nring <= 0) return hipSuccess;
     const int nu = (model == CPG) ? 4 : (model == ONESTEP) ? 5 : ns + 3;
-    if (nu == 4) ring_fill_kernel<4><<<nring, WG, 0, s>>>(a, ring_blocks);
-    else if (nu == 5) ring_fill_kernel<5><<<nring, WG, 0, s>>>(a, ring_blocks);
-    else if (nu == 12) ring_fill_kernel<12><<<nring, WG, 0, s>>>(a, ring_blocks);
+    const dim3 grid(nring, RESTRICT_SPLIT);
+    if (nu == 4) ring_fill_kernel<4><<<grid, WG, 0, s>>>(a, ring_blocks);
+    else if (nu == 5) ring_fill_kernel<5><<<grid, WG, 0, s>>>(a, ring_blocks);
+    else if (nu == 12) ring_fill_kernel<12><<<grid, WG, 0, s>>>(a, ring_blocks);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
