@@ -255,20 +255,22 @@ __device__ __forceinline__ unsigned owner_state(const double (&u)[NU], double Tp
     return st;
 }
 
-// WENO5-JS at i+1/2 from f_{i-2..i+2}: the weighted average of the three
-// candidate stencils in common-denominator form (one division).
+// WENO5-JS at i+1/2 from f_{i-2..i+2} (a..e), written in first differences
+// d1..d4: the candidate values are c + r_k / 6, the smoothness indicators times 12
+// are 13 (second difference)^2 + 3 (one-sided slope)^2 (the common factor 144 of
+// the squared (eps + beta) cancels in the normalized weights), and the weighted
+// average is c + sum w_k r_k / (6 sum w_k) with the weights in common-denominator
+// form (one division). Algebraically the textbook form; fewer operations.
 __device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
-    const double q0 = 2.0 * a - 7.0 * b + 11.0 * c;
-    const double q1 = -b + 5.0 * c + 2.0 * d;
-    const double q2 = 2.0 * c + 5.0 * d - e;
-    const double t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
-    const double t1 = b - 2.0 * c + d, u1 = b - d;
-    const double t2 = c - 2.0 * d + e, u2 = 3.0 * c - 4.0 * d + e;
-    const double s0 = sq(WENO_EPS + ((13.0 / 12.0) * t0 * t0 + 0.25 * u0 * u0));
-    const double s1 = sq(WENO_EPS + ((13.0 / 12.0) * t1 * t1 + 0.25 * u1 * u1));
-    const double s2 = sq(WENO_EPS + ((13.0 / 12.0) * t2 * t2 + 0.25 * u2 * u2));
+    const double d1 = b - a, d2 = c - b, d3 = d - c, d4 = e - d;
+    const double r0 = 5.0 * d2 - 2.0 * d1, r1 = d2 + 2.0 * d3, r2 = 4.0 * d3 - d4;
+    const double t0 = d2 - d1, t1 = d3 - d2, t2 = d4 - d3;
+    const double u0 = 3.0 * d2 - d1, u1 = d2 + d3, u2 = d4 - 3.0 * d3;
+    const double s0 = sq((12.0 * WENO_EPS + 13.0 * t0 * t0) + 3.0 * u0 * u0);
+    const double s1 = sq((12.0 * WENO_EPS + 13.0 * t1 * t1) + 3.0 * u1 * u1);
+    const double s2 = sq((12.0 * WENO_EPS + 13.0 * t2 * t2) + 3.0 * u2 * u2);
     const double w0 = 0.1 * (s1 * s2), w1 = 0.6 * (s0 * s2), w2 = 0.3 * (s0 * s1);
-    return (w0 * q0 + w1 * q1 + w2 * q2) / (6.0 * (w0 + w1 + w2));
+    return c + (w0 * r0 + w1 * r1 + w2 * r2) / (6.0 * (w0 + w1 + w2));
 }
 
 __device__ __forceinline__ double rk_combine(int stage, double u0, double us, double L, double dt) {
