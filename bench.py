@@ -105,10 +105,23 @@ def cpu_baseline(case, steps, target_s=10.0, max_steps=20):
             el += time.perf_counter() - t1
             steps += more
     cells = case.valid_cells()
-    return {"value": cells * 3 * steps / el, "unit": "cell-stage/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{steps} step(s) of the same {len(case.blocks)}-block AMR workload "
-                      f"({cells} cells), OpenMP over all host threads, {el:.1f} s"}
+    out = {"value": cells * 3 * steps / el, "unit": "cell-stage/s",
+           "cores": oracle.max_threads(), "kind": "oracle",
+           "sample": f"{steps} step(s) of the same {len(case.blocks)}-block AMR workload "
+                     f"({cells} cells), OpenMP over all host threads, {el:.1f} s"}
+    # the same oracle on one host thread, one step
+    nthreads = oracle.max_threads()
+    oracle.set_threads(1)
+    try:
+        U1, T1 = oracle.block_state(case)
+        t0 = time.perf_counter()
+        oracle.step_blocks(case, U1, T1, 1)
+        el1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(nthreads)
+    out["one_thread"] = {"value": cells * 3 / el1, "unit": "cell-stage/s",
+                         "sample": f"1 step of the same workload on 1 thread, {el1:.1f} s"}
+    return out
 
 
 def main():
