@@ -205,3 +205,19 @@ def test_full_jacobian_amr_detailed_vs_oracle():
 def test_full_jacobian_strang_crossover_vs_oracle():
     _cmp_blocks(_small_detailed_amr(), 2, crossover=True, split=janc.SPLIT_STRANG,
                 jac=janc.JAC_FULL)
+
+
+# ------------------------------------------------------------------ full-size workloads
+def test_full_amr_workload_vs_oracle():
+    """The timed 9-species AMR workload (637 blocks, 1,975,360 cells) in the launch form the
+    benchmark times (batched tiles, graph replay), element by element."""
+    _cmp_blocks(amr_case(), 2)
+
+
+def test_full_amr_workload_crossover_vs_oracle():
+    _cmp_blocks(amr_case(), 1, crossover=True)
+
+
+def test_full_ensemble_vs_oracle():
+    """All 64 instances (32 1-D, 32 2-D) of the ensemble workload."""
+    _cmp_blocks(ensemble_case(), 5)
