@@ -40,16 +40,16 @@ struct Geom {
     static constexpr int NYS = TWO ? TX * (TY + 6) : 0; // y split fluxes, 3 halo rows
     static constexpr int NIX = (TX + 1) * TY;           // x interfaces
     static constexpr int NIY = TWO ? TX * (TY + 1) : 0; // y interfaces
-    static constexpr int NEXT = 2 * TY + (TWO ? 2 * TX : 0);  // right column / top row, both sides
-    // LDS doubles of one set: F+/F- and G+/G-, the four one-sided interface values;
-    // NSET sets (two: the next component's fluxes are written while this one is
-    // reconstructed, one barrier per component), then scratch
-    static constexpr int SET = 2 * NXS + 2 * NYS + 2 * NIX + 2 * NIY;
+    static constexpr int NEXT = TY + (TWO ? TX : 0);  // right column / top row interfaces
+    // LDS doubles of one set: F+/F- and G+/G-, then the numerical fluxes (sum of the
+    // two one-sided reconstructions) at the x and y interfaces; NSET sets (two: the
+    // next component's fluxes are written while this one is reconstructed, one
+    // barrier per component), then scratch
+    static constexpr int SET = 2 * NXS + 2 * NYS + NIX + NIY;
     static constexpr int NSET = STAGE_SETS;
     static constexpr int LDS = NSET * SET + 16;
     static constexpr int oFPX = 0, oFMX = NXS, oFPY = 2 * NXS, oFMY = 2 * NXS + NYS;
-    static constexpr int oHXP = 2 * NXS + 2 * NYS, oHXM = oHXP + NIX, oHYP = oHXM + NIX,
-                         oHYM = oHYP + NIY;
+    static constexpr int oHX = 2 * NXS + 2 * NYS, oHY = oHX + NIX;
 
     // tile-local position (li, lj) of point p
     __device__ static void point(int p, int& li, int& lj) {
@@ -154,23 +154,24 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
     const int bxi = olj * G::PW + oli, byi = olj * TX + oli;
     const int rxi = olj * (TX + 1) + oli, ryi = olj * TX + oli;
     bool ext_ok = false;
-    int ext_str = 1, ext_in = 0, ext_out = 0;   // offsets within a set
+    int ext_str = 1, ext_p = 0, ext_m = 0, ext_out = 0;   // offsets within a set
     if (tid < G::NEXT) {
         const int e = tid;
-        if (e < 2 * TY) {          // x interface TX of row e % TY, F+ then F-
-            const int side = e / TY, row = e - side * TY;
-            ext_ok = row < th && tw == TX;
-            const int r = row * (TX + 1) + TX, o = row * G::PW + TX;
-            ext_in = side ? G::oFMX + o + 5 : G::oFPX + o;
-            ext_str = side ? -1 : 1;
-            ext_out = (side ? G::oHXM : G::oHXP) + r;
-        } else {                   // y interface TY of column, F+ then F-
-            const int h = e - 2 * TY, side = h / TX, col = h - side * TX;
+        if (e < TY) {              // x interface TX of row e
+            ext_ok = e < th && tw == TX;
+            const int o = e * G::PW + TX;
+            ext_p = G::oFPX + o;
+            ext_m = G::oFMX + o;
+            ext_str = 1;
+            ext_out = G::oHX + e * (TX + 1) + TX;
+        } else {                   // y interface TY of column e - TY
+            const int col = e - TY;
             ext_ok = col < tw && th == TY;
-            const int r = TY * TX + col, o = TY * TX + col;
-            ext_in = side ? G::oFMY + o + 5 * TX : G::oFPY + o;
-            ext_str = side ? -TX : TX;
-            ext_out = (side ? G::oHYM : G::oHYP) + r;
+            const int o = TY * TX + col;
+            ext_p = G::oFPY + o;
+            ext_m = G::oFMY + o;
+            ext_str = TX;
+            ext_out = G::oHY + TY * TX + col;
         }
     }
 
@@ -205,42 +206,44 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
             }
         }
     };
-    // one-sided WENO5 reconstructions from set S into set S: each thread takes the
-    // left x interface and the lower y interface of its own position (both sides,
-    // fixed LDS offsets); the right column and top row of interfaces are the extra
-    // tasks of the first threads. F- reads its stencil mirrored.
+    // WENO5 reconstructions from set S into set S: each thread takes the left x
+    // interface and the lower y interface of its own position (both one-sided values,
+    // summed: the numerical flux), at fixed LDS offsets; the right column and top row
+    // of interfaces are the extra tasks of the first threads. F- reads its stencil
+    // mirrored.
     auto recon = [&](double* S) {
         if (vxi) {
             const double* P = S + G::oFPX + bxi;
             const double* Mn = S + G::oFMX + bxi;
-            S[G::oHXP + rxi] = weno5(P[0], P[1], P[2], P[3], P[4]);
-            S[G::oHXM + rxi] = weno5(Mn[5], Mn[4], Mn[3], Mn[2], Mn[1]);
+            S[G::oHX + rxi] = weno5(P[0], P[1], P[2], P[3], P[4]) +
+                              weno5(Mn[5], Mn[4], Mn[3], Mn[2], Mn[1]);
         }
         if constexpr (G::TWO) {
             if (vyi) {
                 const double* P = S + G::oFPY + byi;
                 const double* Mn = S + G::oFMY + byi;
-                S[G::oHYP + ryi] = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX]);
-                S[G::oHYM + ryi] = weno5(Mn[5 * TX], Mn[4 * TX], Mn[3 * TX], Mn[2 * TX], Mn[TX]);
+                S[G::oHY + ryi] = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX]) +
+                                  weno5(Mn[5 * TX], Mn[4 * TX], Mn[3 * TX], Mn[2 * TX], Mn[TX]);
             }
         }
         if (ext_ok) {
-            const double* b = S + ext_in;
-            S[ext_out] = weno5(b[0], b[ext_str], b[2 * ext_str], b[3 * ext_str], b[4 * ext_str]);
+            const double* P = S + ext_p;
+            const double* Mn = S + ext_m;
+            const int k = ext_str;
+            S[ext_out] = weno5(P[0], P[k], P[2 * k], P[3 * k], P[4 * k]) +
+                         weno5(Mn[5 * k], Mn[4 * k], Mn[3 * k], Mn[2 * k], Mn[k]);
         }
     };
     // flux difference (Eq. 4.10), source and RK stage of component f from set S
     auto update = [&](int f, const double* S, double u0) {
         if (own) {
-            const double* hxp = S + G::oHXP;
-            const double* hxm = S + G::oHXM;
+            const double* hx = S + G::oHX;
             const int rx = olj * (TX + 1) + oli;
-            double L = -((hxp[rx + 1] + hxm[rx + 1]) - (hxp[rx] + hxm[rx])) * idx;
+            double L = -(hx[rx + 1] - hx[rx]) * idx;
             if constexpr (G::TWO) {
-                const double* hyp = S + G::oHYP;
-                const double* hym = S + G::oHYM;
+                const double* hy = S + G::oHY;
                 const int ry = olj * TX + oli;
-                L -= ((hyp[ry + TX] + hym[ry + TX]) - (hyp[ry] + hym[ry])) * idy;
+                L -= (hy[ry + TX] - hy[ry]) * idy;
             }
             if constexpr (M == ONESTEP) {
                 if (f == 4) L += src_e;
