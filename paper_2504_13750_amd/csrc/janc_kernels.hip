@@ -410,6 +410,7 @@ __device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, dou
                 T * (0.5 * a[1] + T * (a[2] * (1.0 / 6.0) + T * (a[3] * (1.0 / 12.0) + T * (a[4] * 0.05)))) +
                 a[5] * invT - a[6];
     }
+    gts[NS * WG + tid] = 0.0;   // padding slot of the molecule lists
     // species + T Jacobian: T follows the composition at fixed rho and e, so
     // J += (dS/dT) (dT/d rho Y)^T with dT/d rho Y_m = -(e_m - e_last) / (rho c_v);
     // hm1[j] = h_j/(R_u T) - 1 = e_j / (R_u T) per mole, cvs = rho c_v / R_u
@@ -440,16 +441,17 @@ __device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, dou
     for (int i = 0; i < nr; ++i) {
         const double lnkf = m->lnA[i] + m->b[i] * lnT - m->EaR[i] * invT;
         const double kf = exp(lnkf);
+        const int f0 = m->lf[i][0], f1 = m->lf[i][1], f2 = m->lf[i][2];
+        const int r0 = m->lb[i][0], r1 = m->lb[i][1], r2 = m->lb[i][2];
         double kb = 0.0;
         if (m->rev[i]) {
-            double sg = 0.0;
-#pragma unroll
-            for (int j = 0; j < NS; ++j) sg += (double)m->dnu[i][j] * gts[j * WG + tid];
+            // sum_j dnu_j g_j, g = h/(RT) - s/R: products minus reactants, one entry per
+            // molecule (the padding slot holds 0)
+            const double sg = (gts[r0 * WG + tid] + gts[r1 * WG + tid] + gts[r2 * WG + tid]) -
+                              (gts[f0 * WG + tid] + gts[f1 * WG + tid] + gts[f2 * WG + tid]);
             // K_eq = exp(-sum dnu g) (p_atm/(R_u T))^(sum dnu), Eq. 4.9
             kb = exp(lnkf + sg - (double)m->dnsum[i] * lnC);
         }
-        const int f0 = m->lf[i][0], f1 = m->lf[i][1], f2 = m->lf[i][2];
-        const int r0 = m->lb[i][0], r1 = m->lb[i][1], r2 = m->lb[i][2];
         const double xf0 = Xs[f0 * WG + tid], xf1 = Xs[f1 * WG + tid], xf2 = Xs[f2 * WG + tid];
         const double xb0 = Xs[r0 * WG + tid], xb1 = Xs[r1 * WG + tid], xb2 = Xs[r2 * WG + tid];
         const double Rf = kf * (xf0 * xf1 * xf2), Rb = kb * (xb0 * xb1 * xb2);
@@ -548,7 +550,7 @@ template <int NS, bool FULLJ>
 __global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
     constexpr int NU = NS + 3;
     __shared__ double Xs[(NS + 1) * WG];
-    __shared__ double gts[NS * WG];
+    __shared__ double gts[(NS + 1) * WG];
     __shared__ double dqs[(NS + 1) * WG];
     __shared__ double scratch[16];
     const Tile tile = a.tiles[blockIdx.x];
