@@ -103,3 +103,39 @@ def test_regrid_rejects_bad_parameters():
         assert ei.value.code == -1
     plan.close()
     ctx.close()
+
+
+def test_adaptive_run_vs_oracle():
+    """Steps with a layer update every 4 steps (AdaptiveRun) against the oracle doing the
+    same sequence: 10 steps, updates after steps 4 and 8."""
+    from paper_2504_13750_amd.amr import AdaptiveRun
+    c = _small_detailed_amr()
+    thr, buf, sub = PARAMS["front-9sp-3lev"]
+    print("[gpu] AdaptiveRun front-9sp-3lev, 10 steps, update every 4", flush=True)
+    torch, dev = torch_dev()
+    ctx = context_for(c)
+    U, T = init_blocks(ctx, c)
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    run = AdaptiveRun(ctx, janc.domains_of(c), c.blocks, c.pool_cells, U, T, janc.time_of(c), t,
+                      (thr, buf, sub), every=4)
+    run.advance(3)
+    run.advance(7)
+    ctx.sync_status()
+    assert run.steps == 10 and run.updates == 2
+    Uo, To = oracle.block_state(c)
+    n, to = c, None
+    for chunk in (4, 4, 2):
+        Uo, To, to, _, _ = oracle.step_blocks(n, Uo, To, chunk, t=to)
+        if chunk == 4:
+            ob, opool = oracle.regrid(n, Uo, thr, buf, sub)
+            Uo, To = oracle.regrid_fill(n, Uo, To, ob, opool)
+            n = _with_table(c, ob, opool)
+    assert _table(run.blocks) == _table(n.blocks)
+    e = rel_err(run.U.cpu().numpy(), Uo)
+    eT = rel_err(run.T.cpu().numpy()[None], To[None])[0]
+    print(f"  adaptive run: {len(run.blocks)} blocks, per-field rel err "
+          f"{np.array2string(e, precision=2)}, T {eT:.2e}", flush=True)
+    assert np.all(e <= TOL) and eT <= TOL
+    assert t.item() == pytest.approx(to[0], rel=1e-12)
+    run.close()
+    ctx.close()
