@@ -139,3 +139,32 @@ def test_adaptive_run_vs_oracle():
     assert t.item() == pytest.approx(to[0], rel=1e-12)
     run.close()
     ctx.close()
+
+
+def test_adaptive_run_crossover_vs_oracle():
+    """The same with the crossover advance (a step is one level-0 step)."""
+    from paper_2504_13750_amd.amr import AdaptiveRun
+    c = _small_detailed_amr()
+    thr, buf, sub = PARAMS["front-9sp-3lev"]
+    print("[gpu] AdaptiveRun crossover front-9sp-3lev, 3 steps, update every 2", flush=True)
+    torch, dev = torch_dev()
+    ctx = context_for(c)
+    U, T = init_blocks(ctx, c)
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    run = AdaptiveRun(ctx, janc.domains_of(c), c.blocks, c.pool_cells, U, T, janc.time_of(c), t,
+                      (thr, buf, sub), every=2, flags=janc.PLAN_CROSSOVER)
+    run.advance(3)
+    ctx.sync_status()
+    Uo, To = oracle.block_state(c)
+    Uo, To, to, _, _ = oracle.step_blocks(c, Uo, To, 2, crossover=True)
+    ob, opool = oracle.regrid(c, Uo, thr, buf, sub)
+    Uo, To = oracle.regrid_fill(c, Uo, To, ob, opool)
+    n = _with_table(c, ob, opool)
+    Uo, To, to, _, _ = oracle.step_blocks(n, Uo, To, 1, t=to, crossover=True)
+    assert _table(run.blocks) == _table(ob)
+    e = rel_err(run.U.cpu().numpy(), Uo)
+    print(f"  adaptive crossover run: per-field rel err {np.array2string(e, precision=2)}",
+          flush=True)
+    assert np.all(e <= TOL)
+    run.close()
+    ctx.close()
