@@ -182,3 +182,42 @@ def test_adjoint_config5_full():
         fd = (Lp - Lm) / (2 * h)
         print(f"  d/d{name}: adjoint {gth[q]:.10e} fd {fd:.10e}", flush=True)
         assert gth[q] == pytest.approx(fd, rel=1e-5, abs=0.0)
+
+
+def test_probe_loss_autograd_function():
+    """torch autograd through the adjoint: gradients equal janc_adjoint's and the oracle's
+    tangents; a few Adam steps on (Q, E_a) lower the loss toward a target trajectory's."""
+    import torch
+    from paper_2504_13750_amd.autograd import probe_loss
+    c, probes, w = _small()
+    _, dev = torch_dev()
+    ctx = janc.Context(janc.ONESTEP)
+    g = janc.grid_of(c)
+    W0 = torch.tensor(c.W, dtype=torch.float64, device=dev, requires_grad=True)
+    theta = torch.tensor([c.Q, c.Ea], dtype=torch.float64, device=dev, requires_grad=True)
+    L = probe_loss(ctx, g, c.gamma, c.R, c.k, c.dt_fixed, W0, theta, 12, 5, probes, w)
+    gW, gth = torch.autograd.grad(3.0 * L, (W0, theta))
+    Ld, gWd, gthd = _gpu_adjoint(c, 12, probes, w, ckpt=5)
+    assert L.item() == Ld
+    assert np.array_equal(gW.cpu().numpy(), 3.0 * gWd) and np.array_equal(gth.cpu().numpy(), 3.0 * gthd)
+    _, dQ = oracle.loss_tangent(c, c.W, 12, probes, w, c.dt_fixed, dQ=1.0)
+    assert gth[0].item() == pytest.approx(3.0 * dQ, rel=1e-10)
+    # inverse problem in the paper's manner (Sec. 6.2, Adam): recover Q from the probes
+    target = probe_loss(ctx, g, c.gamma, c.R, c.k, c.dt_fixed, W0.detach(),
+                        torch.tensor([c.Q, c.Ea], dtype=torch.float64, device=dev), 12, 5,
+                        probes, w).detach()
+    q = torch.tensor([c.Q * 1.1, c.Ea], dtype=torch.float64, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([q], lr=0.5, eps=1e-30)   # the misfit is tiny in absolute terms
+    errs = []
+    for _ in range(8):
+        opt.zero_grad()
+        mis = (probe_loss(ctx, g, c.gamma, c.R, c.k, c.dt_fixed, W0.detach(), q, 12, 5, probes,
+                          w) - target) ** 2
+        mis.backward()
+        opt.step()
+        errs.append(mis.item())
+    print(f"  Adam on Q: misfit {errs[0]:.3e} -> {errs[-1]:.3e}, Q {q[0].item():.4f} "
+          f"(true {c.Q})", flush=True)
+    assert errs[-1] < 0.1 * errs[0]
+    assert abs(q[0].item() - c.Q) < 0.5 * abs(1.1 * c.Q - c.Q)
+    ctx.close()
