@@ -221,3 +221,32 @@ def test_full_amr_workload_crossover_vs_oracle():
 def test_full_ensemble_vs_oracle():
     """All 64 instances (32 1-D, 32 2-D) of the ensemble workload."""
     _cmp_blocks(ensemble_case(), 5)
+
+
+# ------------------------------------------------------------------ profiling entry point
+def test_profile_step_advances_like_a_step():
+    """janc_profile_step takes one step (after the call-entry T solve) exactly as
+    janc_step_blocks does, and reports six non-negative durations; crossover plans and
+    Strang splitting are rejected."""
+    import torch
+    from gpu_util import init_blocks, context_for
+    bc = _small_detailed_amr()
+    Ua, Ta, ta = run_blocks(bc, 1, flags=janc.PLAN_NO_GRAPH)
+    print("[gpu] janc_profile_step amr128x64L3", flush=True)
+    ctx = context_for(bc)
+    plan = ctx.plan(janc.domains_of(bc), bc.blocks, bc.pool_cells)
+    U, T = init_blocks(ctx, bc)
+    t = torch.zeros(1, dtype=torch.float64, device=U.device)
+    ms = ctx.profile_step(plan, janc.time_of(bc), U, T, t)
+    ctx.sync_status()
+    assert len(ms) == 6 and all(x >= 0.0 for x in ms) and ms[0] > 0.0 and ms[3] > 0.0
+    assert np.array_equal(U.cpu().numpy(), Ua) and np.array_equal(T.cpu().numpy(), Ta)
+    assert t.item() == ta[0]
+    with pytest.raises(janc.JancError):
+        ctx.profile_step(plan, janc.time_of(bc, split=janc.SPLIT_STRANG), U, T, t)
+    xplan = ctx.plan(janc.domains_of(bc), bc.blocks, bc.pool_cells, janc.PLAN_CROSSOVER)
+    with pytest.raises(janc.JancError):
+        ctx.profile_step(xplan, janc.time_of(bc), U, T, t)
+    xplan.close()
+    plan.close()
+    ctx.close()
