@@ -159,6 +159,19 @@ def test_status_flag_on_negative_density():
     assert ei.value.code == -6
 
 
+def test_status_flag_on_non_finite_state():
+    """A NaN density is reported as JANC_ENONFINITE through the sticky status word, and the
+    word is cleared once read."""
+    import paper_2504_13750_amd as janc
+    c = detonation_tube_case(nx=32, ny=8, seed=1)
+    c.W[0, 4, 10] = float("nan")
+    with pytest.raises(janc.JancError) as ei:
+        run_uniform(c, 1)
+    assert ei.value.code == -4
+    ok = detonation_tube_case(nx=32, ny=8, seed=1)
+    run_uniform(ok, 1)        # a fresh context reports no stale status
+
+
 def test_detailed_front_strang_splitting():
     c = detailed_front_case(nx=48, ny=40)
     _compare(c, 4, split=1)
