@@ -136,6 +136,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-crossover", action="store_true")
     ap.add_argument("--no-regrid", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
@@ -326,6 +327,54 @@ def main():
             f"updated hierarchy {1e3 * r_s / rsteps:.3f} ms/step")
         nplan.close()
 
+    # ------------------------------------------------------------ ensemble batching
+    ensemble = None
+    if not args.no_ensemble:
+        from cases import ensemble_case
+        ens = ensemble_case()
+        ectx = janc.Context(janc.ONESTEP)
+        eplan = ectx.plan(janc.domains_of(ens), ens.blocks, ens.pool_cells, janc.PLAN_DEFAULT)
+        We = torch.tensor(ens.W, dtype=torch.float64, device=dev)
+        Ue = torch.empty_like(We)
+        Te = torch.empty(ens.pool_cells, dtype=torch.float64, device=dev)
+        flops, ecells = 0.0, 0
+        for b in ens.blocks:
+            dom = ens.domains[int(b["domain"])]
+            s0, n = int(b["offset"]), int(b["nx"]) * int(b["ny"])
+            u, tt = ectx.init_state(janc.physics_of(dom), We[:, s0:s0 + n].contiguous())
+            Ue[:, s0:s0 + n] = u
+            Te[s0:s0 + n] = tt
+            flops += n * stage_flops(1, 5, dom.ny > 1)
+            ecells += n
+        te = torch.zeros(len(ens.domains), dtype=torch.float64, device=dev)
+        etm = janc.time_of(ens)
+        ectx.step_blocks(eplan, etm, Ue, Te, 2, te)
+        esteps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        ectx.step_blocks(eplan, etm, Ue, Te, esteps, te)
+        e1.record()
+        torch.cuda.synchronize()
+        e_s = e0.elapsed_time(e1) / 1e3
+        est = float(np.mean([np.mean(ectx.profile_step(eplan, etm, Ue, Te, te)[0:3])
+                             for _ in range(2)]))
+        ectx.sync_status()
+        tf = flops / (est * 1e-3) / 1e12
+        gbs = ecells * stage_bytes(5) / (est * 1e-3) / 1e9
+        ensemble = {"workload": f"{len(ens.domains)} one-step instances "
+                                f"({sum(d.ny == 1 for d in ens.domains)} 1-D), {ecells} cells",
+                    "ms_per_step": 1e3 * e_s / esteps, "steps": esteps,
+                    "cell_stage_per_s": ecells * 3 * esteps / e_s,
+                    "stage_kernel_ms": est, "fp64_tflops": tf,
+                    "fp64_frac": tf / PEAK_FP64_VALU_TFLOPS,
+                    "hbm_algorithmic_GBs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+        log(f"[bench] ensemble {ensemble['workload']}: {ensemble['ms_per_step']:.3f} ms/step, "
+            f"{ensemble['cell_stage_per_s']:.3e} cell-stage/s; stage kernel {est:.3f} ms = "
+            f"{tf:.2f} TFLOP/s ({100 * tf / PEAK_FP64_VALU_TFLOPS:.1f} %), {gbs:.0f} GB/s algorithmic")
+        eplan.close()
+        ectx.close()
+
     # ------------------------------------------------------------ adjoint / forward cost
     adjoint = None
     if not args.no_adjoint:
@@ -421,6 +470,7 @@ def main():
         "per_block": per_block,
         "crossover": crossover,
         "regrid": regrid,
+        "ensemble": ensemble,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
         "context": "paper (A100, real H2-O2 mechanism, 2.76 M cells incl. invalid blocks): "
