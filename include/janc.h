@@ -59,11 +59,13 @@ enum { JANC_MAX_FIELDS = 16, JANC_MAX_LEVELS = 8, JANC_MAX_PROBES = 8 };
 
 /* Detailed mechanism (host arrays, copied at janc_create), SI units:
  * M [ns] kg/mol; nasa [ns][7] NASA-7 coefficients a0..a6 (Eq. 4.3-4.5): the
- * only set, or with nasa_high / t_mid the low-temperature set (T < t_mid); A [nr] in (m^3/mol)^(order-1)/s; b [nr]; Ea [nr] J/mol
- * (Eq. 4.8); nu_f, nu_b [nr][ns] integer stoichiometry (Eq. 4.6); tb [nr][ns]
- * third-body efficiencies, used when has_tb[i] (Eq. 4.7); reversible [nr]:
- * k_b = k_f / K_eq (Eq. 4.9) when set, else 0. The last species is the
- * complement 1 - sum(Y). Supported ns: 2..12 (compiled sizes), nr <= 64. */
+ * only set, or with nasa_high / t_mid the low-temperature set (T < t_mid);
+ * A [nr] in (m^3/mol)^(order-1)/s; b [nr]; Ea [nr] J/mol (Eq. 4.8); nu_f, nu_b
+ * [nr][ns] integer stoichiometry (Eq. 4.6), at most 3 molecules per side;
+ * tb [nr][ns] third-body efficiencies, used when has_tb[i] (Eq. 4.7);
+ * reversible [nr]: k_b = k_f / K_eq (Eq. 4.9) when set, else 0. The last
+ * species is the complement 1 - sum(Y). Kernels are compiled for ns = 2 and
+ * ns = 9 (other sizes: JANC_EINVAL); nr <= 64. */
 typedef struct {
     int ns, nr;
     const double *M, *nasa, *A, *b, *Ea;
@@ -142,7 +144,8 @@ janc_status janc_init_state(janc_ctx *ctx, const janc_physics *phys, long long n
                             const double *W, double *U, double *T, void *stream);
 
 /* nsteps steps of the full update on a uniform grid (Sec. 4.3 advance_one_step:
- * CFL, RK3 flux stages, then chemistry for DETAILED). U (device) [nfields][ny][nx]
+ * CFL, RK3 flux stages, then chemistry for DETAILED; with JANC_SPLIT_STRANG the
+ * chemistry takes half steps before and after the stages). U (device) [nfields][ny][nx]
  * and T (device) [ny][nx] are updated in place; T is re-solved from U at entry
  * with the given T as the Newton warm start. t (device) [1] is advanced by each
  * dt. dt_log (device) [nsteps] receives each dt, or may be NULL. */
