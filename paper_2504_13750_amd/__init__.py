@@ -8,6 +8,23 @@ library every call raises.
 
 Paper: "JANC: A cost-effective, differentiable compressible reacting flow
 solver featured with JAX-based adaptive mesh refinement", arXiv 2504.13750.
+
+Minimal use (a 9-species mechanism read from chemkin text, one uniform grid)::
+
+    import torch, paper_2504_13750_amd as janc
+    from paper_2504_13750_amd import chemkin
+    mech = chemkin.parse(open("mech.inp").read(), open("thermo.dat").read())
+    ctx = janc.Context(janc.DETAILED, mech)
+    grid = janc.make_grid(nx, ny, dx, dy, [janc.BC_ZEROGRAD] * 4, [None] * 4)
+    phys = janc.make_physics()
+    U, T = ctx.init_state(phys, W)            # W: [p, u, v, T, Y_1..Y_{Ns-1}] on cuda:0
+    t = torch.zeros(1, dtype=torch.float64, device=W.device)
+    ctx.step(grid, phys, janc.make_time(cfl=0.5, split=janc.SPLIT_STRANG), U, T, 100, t)
+    ctx.sync_status()
+
+Block tables (AMR hierarchies, ensembles): Context.plan + Context.step_blocks; layer
+updates: Context.regrid + Context.regrid_fill, or amr.AdaptiveRun for the time loop;
+gradients: Context.adjoint, or autograd.probe_loss inside torch autograd.
 """
 
 import ctypes as C
