@@ -168,3 +168,23 @@ def test_adaptive_run_crossover_vs_oracle():
     assert np.all(e <= TOL)
     run.close()
     ctx.close()
+
+
+def test_regrid_capacity_reported():
+    """janc_regrid with too small an output table returns JANC_EINVAL and the length needed."""
+    import ctypes as C
+    from paper_2504_13750_amd import _lib as L
+    c = _base_case(jump_at=77)
+    ctx = context_for(c)
+    plan = ctx.plan(janc.domains_of(c), c.blocks, c.pool_cells)
+    U, T = init_blocks(ctx, c)
+    full, pool = ctx.regrid(plan, U, 0.01, 3, 8)
+    out = np.zeros(2, dtype=janc.BLOCK_DTYPE)
+    n, p = C.c_int(0), C.c_longlong(0)
+    params = L.janc_regrid_params(0.01, 3, 8)
+    st = L.lib().janc_regrid(ctx.h, plan.h, C.byref(params), C.c_void_p(U.data_ptr()),
+                             out.ctypes.data_as(C.c_void_p), 2, C.byref(n), C.byref(p),
+                             C.c_void_p(torch_dev()[0].cuda.current_stream().cuda_stream))
+    assert st == -1 and n.value == len(full) and p.value == pool
+    plan.close()
+    ctx.close()
