@@ -43,6 +43,13 @@
  *     the RK stages and half after them, with dt from the step-start state.
  *   - regridding masks cells by a normalized central density difference and
  *     refines fixed subregions of each block (see the regridding section).
+ *
+ * Parity unpinned: the coarse-fine coupling of partially refined hierarchies (ring
+ * cells read from the coarser level, and in the crossover advance the coarser level's
+ * state held while a finer level steps) has no closed form or independent reference.
+ * Its pins cover the special cases only: full refinement equals the fine uniform
+ * grid, restriction is the four-child mean, a constant state survives, one level
+ * equals the uniform grid; beyond these the GPU is checked against this code alone.
  */
 #include <cmath>
 #include <cstdint>
