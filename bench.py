@@ -90,6 +90,16 @@ def measured_traffic():
     return float(val) if hsh == kernel_source_hash() else None
 
 
+def optional(name, fn):
+    """Run an optional section of the benchmark: a failure is logged and recorded in its
+    place, and the headline measurement is still printed."""
+    try:
+        return fn()
+    except Exception as e:  # noqa: BLE001
+        log(f"[bench] {name} failed: {type(e).__name__}: {e}")
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 def cpu_baseline(case, steps, target_s=10.0, max_steps=20):
     """The oracle on the same workload: `steps` steps, extended to about target_s of work."""
     import oracle
@@ -231,8 +241,8 @@ def main():
         f"restriction {np.mean(restr_ms):.3f} ms, ring {np.mean(ring_ms):.3f} ms")
 
     # ------------------------------------------------------------ per-block launch form
-    per_block = None
-    if not args.no_per_block:
+    def _per_block():
+        per_block = None
         pplan = ctx.plan(domains, case.blocks, case.pool_cells,
                          janc.PLAN_PER_BLOCK | janc.PLAN_NO_GRAPH)
         pb_s, _, _ = timed_run(pplan, args.per_block_steps, 1)
@@ -245,10 +255,12 @@ def main():
         log(f"[bench] per-block form {per_block['ms_per_step']:.3f} ms/step "
             f"-> fused speed-up {value / pb_value:.2f}x")
         pplan.close()
+        return per_block
+    per_block = None if args.no_per_block else optional("per_block", _per_block)
 
     # ------------------------------------------------------------ crossover advance
-    crossover = None
-    if not args.no_crossover:
+    def _crossover():
+        crossover = None
         xplan = ctx.plan(domains, case.blocks, case.pool_cells, janc.PLAN_CROSSOVER)
         xsteps = max(1, args.steps // 4)
         sim_x = []
@@ -269,10 +281,12 @@ def main():
         log(f"[bench] crossover advance {crossover['ms_per_step']:.3f} ms per level-0 step, "
             f"{rate_x / rate_s:.2f}x the synchronous advance in simulated time per second")
         xplan.close()
+        return crossover
+    crossover = None if args.no_crossover else optional("crossover", _crossover)
 
     # ------------------------------------------------------------ layer update (regridding)
-    regrid = None
-    if not args.no_regrid:
+    def _regrid():
+        regrid = None
         thr, buf, sub, every = 0.05, 4, 8, 40
         U0, T0, t0 = fresh_state()
         ctx.step_blocks(plan, tm, U0, T0, 2, t0)
@@ -326,10 +340,12 @@ def main():
             f"blocks, {ncells} cells; every {every} steps: {1e3 * total / every:.3f} ms/step; "
             f"updated hierarchy {1e3 * r_s / rsteps:.3f} ms/step")
         nplan.close()
+        return regrid
+    regrid = None if args.no_regrid else optional("regrid", _regrid)
 
     # ------------------------------------------------------------ ensemble batching
-    ensemble = None
-    if not args.no_ensemble:
+    def _ensemble():
+        ensemble = None
         from cases import ensemble_case
         ens = ensemble_case()
         ectx = janc.Context(janc.ONESTEP)
@@ -374,10 +390,12 @@ def main():
             f"{tf:.2f} TFLOP/s ({100 * tf / PEAK_FP64_VALU_TFLOPS:.1f} %), {gbs:.0f} GB/s algorithmic")
         eplan.close()
         ectx.close()
+        return ensemble
+    ensemble = None if args.no_ensemble else optional("ensemble", _ensemble)
 
     # ------------------------------------------------------------ adjoint / forward cost
-    adjoint = None
-    if not args.no_adjoint:
+    def _adjoint():
+        adjoint = None
         from cases import adjoint_case
         a = adjoint_case()
         ac = a["case"]
@@ -419,12 +437,16 @@ def main():
         log(f"[bench] adjoint {ta * 1e3:.2f} ms vs forward {tf * 1e3:.2f} ms: "
             f"{ta / tf:.2f}x")
         actx.close()
+        return adjoint
+    adjoint = None if args.no_adjoint else optional("adjoint", _adjoint)
 
-    cpu = None
-    if not args.no_cpu_baseline:
+    def _cpu():
+        cpu = None
         log(f"[bench] CPU oracle baseline ({args.cpu_steps} step)")
         cpu = cpu_baseline(case, args.cpu_steps)
         log(f"[bench] oracle {cpu['value']:.4e} cell-stage/s on {cpu['cores']} threads")
+        return cpu
+    cpu = None if args.no_cpu_baseline else optional("cpu", _cpu)
 
     out = {
         "metric": METRIC,
