@@ -250,3 +250,40 @@ def test_profile_step_advances_like_a_step():
     xplan.close()
     plan.close()
     ctx.close()
+
+
+# ------------------------------------------------------------------ maximum refined block
+def _max_block_case(n1):
+    """A 192 x 160 one-step base in 64 x 32 blocks (the base tiles the domain) and one
+    refined block of n1 x n1 fine cells centred on a pressure bump."""
+    nx0, ny0 = 192, 160
+    recs = [(0, 0, i0, j0, 64, 32) for j0 in range(0, ny0, 32) for i0 in range(0, nx0, 64)]
+    i1, j1 = 2 * nx0 // 2 - n1 // 2, 2 * ny0 // 2 - n1 // 2
+    recs.append((0, 1, i1 - i1 % 8, j1 - j1 % 8, n1, n1))
+    parts = []
+    for (_, lev, i0, j0, nx, ny) in recs:
+        dx = 0.05 / (1 << lev)
+        X, Y = np.meshgrid((i0 + np.arange(nx) + 0.5) * dx, (j0 + np.arange(ny) + 0.5) * dx)
+        W = np.zeros((5, ny, nx))
+        W[0] = 1.0
+        W[3] = 1.0 + 2.0 * np.exp(-((X - 4.8) ** 2 + (Y - 4.0) ** 2) / 0.5)
+        W[4] = 1.0
+        parts.append(W.reshape(5, -1))
+    dom = Domain(nx=nx0, ny=ny0, dx=0.05, dy=0.05, bc=[BC_ZEROGRAD] * 2 + [BC_SLIPWALL] * 2,
+                 nlevels=2, gamma=1.2, R=1.0, Q=50.0, Ea=24.0, k=30.0)
+    return BlockCase(name=f"maxblock{n1}", model=MODEL_ONESTEP, domains=[dom],
+                     blocks=make_blocks(recs), W=np.concatenate(parts, axis=1), cfl=0.5)
+
+
+def test_largest_refined_block_vs_oracle():
+    """A refined block of the largest supported size (256 x 256: 32 ring segments per side)."""
+    _cmp_blocks(_max_block_case(256), 6)
+
+
+def test_oversized_refined_block_rejected():
+    bc = _max_block_case(264)
+    ctx = janc.Context(janc.ONESTEP)
+    with pytest.raises(janc.JancError) as ei:
+        ctx.plan(janc.domains_of(bc), bc.blocks, bc.pool_cells)
+    assert ei.value.code == -1
+    ctx.close()
