@@ -287,3 +287,34 @@ def test_oversized_refined_block_rejected():
         ctx.plan(janc.domains_of(bc), bc.blocks, bc.pool_cells)
     assert ei.value.code == -1
     ctx.close()
+
+
+# ------------------------------------------------------------------ several AMR domains
+def _amr_pair():
+    """Two independent 3-level hierarchies (different seeds and pressure levels, so their
+    dt differ) in one block table and pool; returns (pair, first, second)."""
+    a, b = _small_amr(seed=5), _small_amr(seed=9)
+    b.W = b.W.copy()
+    b.W[3] *= 1.5
+    bb = b.blocks.copy()
+    bb["domain"] = 1
+    bb["offset"] += a.pool_cells
+    pair = BlockCase(name="two_amr", model=MODEL_ONESTEP, domains=[a.domains[0], b.domains[0]],
+                     blocks=np.concatenate([a.blocks, bb]), W=np.concatenate([a.W, b.W], axis=1),
+                     cfl=0.5)
+    return pair, a, b
+
+
+def test_two_amr_domains_vs_oracle():
+    _cmp_blocks(_amr_pair()[0], 6)
+
+
+def test_two_amr_domains_crossover_vs_oracle():
+    _cmp_blocks(_amr_pair()[0], 3, crossover=True)
+
+
+def test_amr_domain_alone_equals_in_pair_bitwise():
+    pair, a, b = _amr_pair()
+    Up, _, tp = run_blocks(pair, 4)
+    Ub, _, tb = run_blocks(b, 4)
+    assert np.array_equal(Up[:, a.pool_cells:], Ub) and tp[1] == tb[0] and tp[0] != tp[1]
