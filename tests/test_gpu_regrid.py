@@ -30,9 +30,10 @@ CASES = {
     "bump-3lev": lambda: _base_case(nlevels=3, rho=_smooth_bump),
     "front-9sp-3lev": _small_detailed_amr,
     "amr-9sp-1024x512-full": amr_case,
+    "two-domains-3lev": lambda: __import__("test_gpu_blocks")._amr_pair()[0],
 }
 PARAMS = {"jump-2lev": (0.01, 3, 8), "bump-3lev": (0.02, 4, 8), "front-9sp-3lev": (0.05, 4, 8),
-          "amr-9sp-1024x512-full": (0.05, 4, 8)}
+          "amr-9sp-1024x512-full": (0.05, 4, 8), "two-domains-3lev": (0.005, 4, 8)}
 
 
 @pytest.mark.parametrize("name", list(CASES))
