@@ -87,7 +87,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise LibraryMissing(
                 f"{LIB_PATH} not found: build the HIP library first "
-                "(python -m paper_2504_13750_amd.build or __graft_entry__.build())")
+                "(python -m paper_2504_13750_amd.build)")
         # One HIP runtime per process: torch brings its own; importing it first makes
         # libjanc bind to that runtime instead of loading a second one beside it.
         import torch  # noqa: F401

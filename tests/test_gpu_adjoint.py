@@ -153,7 +153,7 @@ def test_checkpoint_interval_does_not_change_result():
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[2], d[2])
 
 
-def test_adjoint_config5_full():
+def test_adjoint_tube_512x64_400_steps():
     """512 x 64 tube, 400 steps, checkpoints every 20: parameter gradients against the
     oracle's tangents and central differences; a density direction against the oracle."""
     a = adjoint_case()

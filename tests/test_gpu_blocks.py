@@ -118,7 +118,7 @@ def test_amr_detailed_vs_oracle():
     _cmp_blocks(c, 3)
 
 
-@pytest.mark.parametrize("which", ["small", "config3"])
+@pytest.mark.parametrize("which", ["small", "amr-637-blocks"])
 def test_plan_ring_cells_match_oracle(which):
     """Ring-cell counts of the library's segment masks equal the oracle's per-cell rule."""
     bc = _small_amr() if which == "small" else amr_case()

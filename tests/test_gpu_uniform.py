@@ -57,7 +57,7 @@ def test_init_state_parity(model):
 
 
 def test_sod_full_run():
-    """Config 1: 400 cells, CFL 0.5 to t = 0.2 (last step clipped, later steps no-ops)."""
+    """Sod problem: 400 cells, CFL 0.5 to t = 0.2 (last step clipped, later steps no-ops)."""
     c = sod_case()
     _compare(c, 400)
 
@@ -71,7 +71,7 @@ def test_detonation_many_steps_small():
     _compare(detonation_tube_case(nx=128, ny=32, seed=22), 400)
 
 
-def test_detonation_config2_full_size():
+def test_detonation_tube_1024x128_full_size():
     """1024 x 128 tube (the benchmark's uniform workload) for 60 steps."""
     _compare(detonation_tube_case(), 60)
 
