@@ -47,9 +47,11 @@
  * Parity unpinned: the coarse-fine coupling of partially refined hierarchies (ring
  * cells read from the coarser level, and in the crossover advance the coarser level's
  * state held while a finer level steps) has no closed form or independent reference.
- * Its pins cover the special cases only: full refinement equals the fine uniform
- * grid, restriction is the four-child mean, a constant state survives, one level
- * equals the uniform grid; beyond these the GPU is checked against this code alone.
+ * Its pins cover special cases and properties: full refinement equals the fine
+ * uniform grid, restriction is the four-child mean, a constant state survives, one
+ * level equals the uniform grid, mirror-image and transposed hierarchies give
+ * mirror-image and transposed results, and an advected wave crossing a refined band
+ * converges at first order; beyond these the GPU is checked against this code alone.
  */
 #include <cmath>
 #include <cstdint>

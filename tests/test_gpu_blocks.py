@@ -6,7 +6,7 @@ Bar: max relative error per conserved field <= 1e-10 after N steps; the batched
 and per-block launch forms and block splits of a uniform grid are bitwise equal.
 The coarse-fine coupling (ring cells, restriction) has no closed form: its
 parity is against the oracle only ("parity unpinned" beyond the oracle's own
-restriction, full-refinement and constant-state pins).
+restriction, full-refinement, constant-state, symmetry and convergence pins).
 """
 
 import numpy as np
@@ -318,3 +318,29 @@ def test_amr_domain_alone_equals_in_pair_bitwise():
     Up, _, tp = run_blocks(pair, 4)
     Ub, _, tb = run_blocks(b, 4)
     assert np.array_equal(Up[:, a.pool_cells:], Ub) and tp[1] == tb[0] and tp[0] != tp[1]
+
+
+def test_mirror_hierarchy_vs_oracle():
+    """The mirror-pair hierarchy of the oracle's symmetry pin: parity, and the GPU result
+    itself mirror-symmetric."""
+    from test_oracle_amr_symmetry import _mirror_case, _block_data
+    c = _mirror_case()
+    Ug, _ = _cmp_blocks(c, 20)
+    lw0 = c.domains[0].nx
+    for b in c.blocks:
+        lev = int(b["level"])
+        mi = (lw0 << lev) - int(b["i0"]) - int(b["nx"])
+        m = [o for o in c.blocks if o["level"] == lev and o["i0"] == mi and o["j0"] == b["j0"]]
+        A, Bm = _block_data(Ug, b), _block_data(Ug, m[0])[:, :, ::-1]
+        for f in range(5):
+            sgn = -1.0 if f == 1 else 1.0
+            assert np.max(np.abs(A[f] - sgn * Bm[f])) <= 1e-12 * np.max(np.abs(Ug[f])), (lev, f)
+
+
+@pytest.mark.parametrize("crossover", [False, True])
+def test_entropy_wave_refined_band_vs_oracle(crossover):
+    """A density wave advected through a refined band (the oracle's convergence pin)."""
+    from test_oracle_amr_symmetry import _entropy_wave
+    c = _entropy_wave(64)
+    c.dt_fixed = 0.5 / 372
+    _cmp_blocks(c, 60 if crossover else 120, crossover=crossover)

@@ -1,0 +1,193 @@
+"""Pins of the oracle's coarse-fine coupling (Sec. 3.1.3-3.1.4: ring cells take the
+coarser level's value, covered coarse cells the mean of their four children) that
+hold without a closed form of the coupled solution:
+
+* mirror symmetry: a hierarchy and a state that are mirror images about the domain's
+  vertical mid-line (u odd) stay mirror images; an off-by-one parent index, a ring
+  that is wider on one side, or a restriction that reads the wrong child breaks it;
+* transposition: swapping x and y in the table (i0 <-> j0, nx <-> ny), the data of
+  every block and the velocity components transposes the result of an asymmetric
+  3-level hierarchy; an x/y mix-up in the coupling breaks it;
+* convergence: a density wave advected at constant velocity and pressure through a
+  refined band returns the exact translated profile as the grid is refined, at first
+  order or better in the L1 norm over the whole domain; a stale or misplaced
+  injection leaves an O(1) error at the band's edges that does not shrink.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from cases import Domain, BlockCase, MODEL_ONESTEP, MODEL_CPG, BC_PERIODIC, BC_SLIPWALL, \
+    BC_ZEROGRAD
+from cases.common import make_blocks
+from cases.amr import build_hierarchy
+
+DX0 = 0.05
+
+
+def _onestep_state(recs, fn):
+    parts = []
+    for (_, lev, i0, j0, nx, ny) in recs:
+        dx = DX0 / (1 << lev)
+        X, Y = np.meshgrid((i0 + np.arange(nx) + 0.5) * dx, (j0 + np.arange(ny) + 0.5) * dx)
+        parts.append(fn(X, Y).reshape(5, -1))
+    return np.concatenate(parts, axis=1)
+
+
+def _block_data(U, b):
+    return U[:, b["offset"]:b["offset"] + b["nx"] * b["ny"]].reshape(-1, b["ny"], b["nx"])
+
+
+def _mirror_case():
+    """64 x 32 base, levels 1 and 2 placed as mirror pairs about x = 1.6 (level-0 i = 32)."""
+    nx0, ny0 = 64, 32
+    recs = [(0, 0, 0, 0, 32, 32), (0, 0, 32, 0, 32, 32)]
+    lw = [nx0 << l for l in range(3)]
+
+    def pair(lev, i0, j0, nx, ny):
+        return [(0, lev, i0, j0, nx, ny), (0, lev, lw[lev] - i0 - nx, j0, nx, ny)]
+
+    recs += pair(1, 32, 16, 32, 32) + pair(1, 8, 0, 16, 16)
+    recs += pair(2, 80, 40, 32, 32) + pair(2, 96, 72, 16, 16)
+    xc = 0.5 * nx0 * DX0
+
+    def fn(X, Y):
+        W = np.zeros((5,) + X.shape)
+        W[0] = 1.0 + 0.3 * np.exp(-((np.abs(X - xc) - 0.7) ** 2 + (Y - 1.1) ** 2))
+        W[1] = 0.2 * np.sin(2.0 * math.pi * (X - xc) / (nx0 * DX0))
+        W[2] = 0.1 * np.cos(2.0 * Y)
+        W[3] = 1.0 + 2.0 * np.exp(-((np.abs(X - xc) - 0.4) ** 2 + (Y - 0.9) ** 2) / 0.3)
+        W[4] = 1.0
+        return W
+
+    dom = Domain(nx=nx0, ny=ny0, dx=DX0, dy=DX0,
+                 bc=[BC_SLIPWALL, BC_SLIPWALL, BC_ZEROGRAD, BC_SLIPWALL], nlevels=3,
+                 gamma=1.2, R=1.0, Q=50.0, Ea=24.0, k=30.0)
+    return BlockCase(name="mirror", model=MODEL_ONESTEP, domains=[dom], blocks=make_blocks(recs),
+                     W=_onestep_state(recs, fn), cfl=0.5)
+
+
+def test_mirror_symmetric_hierarchy_stays_symmetric(oracle):
+    bc = _mirror_case()
+    blocks = bc.blocks
+    U0, T0 = oracle.block_state(bc)
+    U, T, _, _, _ = oracle.step_blocks(bc, U0, T0, 20)
+    flags = oracle.ring_flags(bc)
+    assert flags.any()
+    lw0 = bc.domains[0].nx
+    assert np.max(np.abs(U[3] - U0[3])) > 1e-3        # the state moved
+    checked = 0
+    for b in blocks:
+        lev = int(b["level"])
+        mi = (lw0 << lev) - int(b["i0"]) - int(b["nx"])
+        m = [n for n, o in enumerate(blocks) if o["level"] == lev and o["i0"] == mi
+             and o["j0"] == b["j0"] and o["nx"] == b["nx"] and o["ny"] == b["ny"]]
+        assert len(m) == 1
+        A, Bm = _block_data(U, b), _block_data(U, blocks[m[0]])[:, :, ::-1]
+        TA, TB = _block_data(T[None], b)[0], _block_data(T[None], blocks[m[0]])[0][:, ::-1]
+        for f in range(5):
+            sgn = -1.0 if f == 1 else 1.0
+            scale = np.max(np.abs(U[f])) + 1e-300
+            assert np.max(np.abs(A[f] - sgn * Bm[f])) <= 1e-12 * scale, (lev, f)
+        assert np.max(np.abs(TA - TB)) <= 1e-12 * np.max(T)
+        checked += 1
+    assert checked == len(blocks)
+
+
+def _transposed(bc):
+    """The same table with x and y swapped."""
+    d = bc.domains[0]
+    recs, parts = [], []
+    U = bc.W
+    for b in bc.blocks:
+        recs.append((0, int(b["level"]), int(b["j0"]), int(b["i0"]), int(b["ny"]), int(b["nx"])))
+        W = _block_data(U, b).transpose(0, 2, 1)[[0, 2, 1, 3, 4]]
+        parts.append(W.reshape(5, -1))
+    dom = Domain(nx=d.ny, ny=d.nx, dx=d.dy, dy=d.dx, bc=[d.bc[2], d.bc[3], d.bc[0], d.bc[1]],
+                 nlevels=d.nlevels, gamma=d.gamma, R=d.R, Q=d.Q, Ea=d.Ea, k=d.k)
+    return BlockCase(name="transposed", model=bc.model, domains=[dom], blocks=make_blocks(recs),
+                     W=np.concatenate(parts, axis=1), cfl=bc.cfl)
+
+
+def test_transposed_hierarchy_gives_transposed_result(oracle):
+    _, geo = build_hierarchy(128, 64, DX0, 3, (1.0, 0.7), blk0=32, seed=8, margin=6)
+    recs = [(0, lev, i0, j0, nx, ny) for (lev, i0, j0, nx, ny) in geo]
+
+    def fn(X, Y):
+        W = np.zeros((5,) + X.shape)
+        W[0] = 1.0 + 0.3 * np.exp(-((X - 3.2) ** 2 + (Y - 1.6) ** 2))
+        W[1] = 0.2 * np.sin(X)
+        W[2] = 0.1 * np.cos(2 * Y)
+        W[3] = 1.0 + 2.0 * np.exp(-((X - 2.0) ** 2 + (Y - 1.0) ** 2) / 0.3)
+        W[4] = 1.0
+        return W
+
+    dom = Domain(nx=128, ny=64, dx=DX0, dy=DX0,
+                 bc=[BC_ZEROGRAD, BC_SLIPWALL, BC_SLIPWALL, BC_ZEROGRAD], nlevels=3,
+                 gamma=1.2, R=1.0, Q=50.0, Ea=24.0, k=30.0)
+    bc = BlockCase(name="amr", model=MODEL_ONESTEP, domains=[dom], blocks=make_blocks(recs),
+                   W=_onestep_state(recs, fn), cfl=0.5)
+    assert (bc.blocks["level"] == 2).any()
+    bt = _transposed(bc)
+    U, T = oracle.block_state(bc)
+    Ut, Tt = oracle.block_state(bt)
+    U, T, t, _, _ = oracle.step_blocks(bc, U, T, 12)
+    Ut, Tt, tt, _, _ = oracle.step_blocks(bt, Ut, Tt, 12)
+    assert tt[0] == pytest.approx(t[0], rel=1e-14)   # dt's two direction terms add in swapped order
+    for b, c in zip(bc.blocks, bt.blocks):
+        A = _block_data(U, b)
+        Bt = _block_data(Ut, c).transpose(0, 2, 1)[[0, 2, 1, 3, 4]]
+        for f in range(5):
+            scale = np.max(np.abs(U[f])) + 1e-300
+            assert np.max(np.abs(A[f] - Bt[f])) <= 1e-12 * scale, (int(b["level"]), f)
+
+
+def _entropy_wave(n):
+    """Periodic density wave, u = 1, v = 0, p = 1, on [0, 1] x [0, 4/n] (slip walls in y);
+    level 1 covers x in [1/4, 3/4) over the full height."""
+    nx0, ny0 = n, 4
+    dx = 1.0 / n
+    recs = [(0, 0, 0, 0, nx0, ny0), (0, 1, nx0 // 2, 0, nx0, 2 * ny0)]
+    parts = []
+    for (_, lev, i0, j0, nx, ny) in recs:
+        h = dx / (1 << lev)
+        X, _ = np.meshgrid((i0 + np.arange(nx) + 0.5) * h, (j0 + np.arange(ny) + 0.5) * h)
+        W = np.zeros((4,) + X.shape)
+        W[0] = 1.0 + 0.2 * np.sin(2.0 * math.pi * X)
+        W[1] = 1.0
+        W[3] = 1.0
+        parts.append(W.reshape(4, -1))
+    dom = Domain(nx=nx0, ny=ny0, dx=dx, dy=dx, bc=[BC_PERIODIC, BC_PERIODIC, BC_SLIPWALL,
+                 BC_SLIPWALL], nlevels=2, gamma=1.4, R=1.0)
+    return BlockCase(name=f"wave{n}", model=MODEL_CPG, domains=[dom], blocks=make_blocks(recs),
+                     W=np.concatenate(parts, axis=1))
+
+
+@pytest.mark.slow
+def test_entropy_wave_through_refined_band_converges(oracle):
+    errs = []
+    for n in (32, 64, 128, 256):
+        bc = _entropy_wave(n)
+        dx1 = 0.5 / n
+        # fixed dt: CFL 0.4 on the fine level, an integer number of steps to t = 1/2
+        nsteps = int(math.ceil(0.5 / (0.4 * dx1 / (1.0 + math.sqrt(1.4 / 0.8)))))
+        dt = 0.5 / nsteps
+        U, T = oracle.block_state(bc)
+        U, T, t, _, _ = oracle.step_blocks(bc, U, T, nsteps, dt_fixed=dt)
+        assert t[0] == pytest.approx(0.5, rel=1e-14)
+        b0 = bc.blocks[0]
+        rho = _block_data(U, b0)[0]                     # level 0 = effective field, restricted
+        x = (np.arange(n) + 0.5) / n
+        exact = 1.0 + 0.2 * np.sin(2.0 * math.pi * (x - 0.5))
+        assert np.max(np.abs(rho - rho[:1, :])) <= 1e-13   # still uniform in y
+        errs.append(np.mean(np.abs(rho[0] - exact)))
+        # velocity and pressure of a contact stay near their constant values
+        mom = _block_data(U, b0)[1]
+        assert np.max(np.abs(mom / rho - 1.0)) < 0.05
+    # first order: the coupling injects piecewise-constant coarse values into the ring and
+    # averages ring children with fine ones, an O(dx) error at the band's inflow edge
+    ratios = [a / b for a, b in zip(errs[:-1], errs[1:])]
+    assert min(ratios) > 1.5 and ratios[-1] > 1.8, errs
+    assert errs[-1] < 1e-2, errs

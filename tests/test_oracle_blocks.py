@@ -10,8 +10,9 @@
   mean of their four children, and a constant state survives a 3-level
   hierarchy unchanged.
 
-The coarse-fine coupling itself has no closed form: beyond these checks its
-parity is "parity unpinned" (oracle and HIP path agree with each other only).
+The coarse-fine coupling itself has no closed form: beyond these checks and the
+symmetry and convergence pins of test_oracle_amr_symmetry.py its parity is
+"parity unpinned" (oracle and HIP path agree with each other only).
 """
 
 import numpy as np
