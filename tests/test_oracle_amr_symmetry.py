@@ -10,8 +10,9 @@ hold without a closed form of the coupled solution:
   3-level hierarchy; an x/y mix-up in the coupling breaks it;
 * convergence: a density wave advected at constant velocity and pressure through a
   refined band returns the exact translated profile as the grid is refined, at first
-  order or better in the L1 norm over the whole domain; a stale or misplaced
-  injection leaves an O(1) error at the band's edges that does not shrink.
+  order or better in the L1 norm over the whole domain, in the synchronous and the
+  crossover advance; a stale or misplaced injection leaves an O(1) error at the band's
+  edges that does not shrink.
 """
 
 import math
@@ -166,16 +167,22 @@ def _entropy_wave(n):
 
 
 @pytest.mark.slow
-def test_entropy_wave_through_refined_band_converges(oracle):
+@pytest.mark.parametrize("crossover", [False, True])
+def test_entropy_wave_through_refined_band_converges(oracle, crossover):
     errs = []
     for n in (32, 64, 128, 256):
         bc = _entropy_wave(n)
         dx1 = 0.5 / n
-        # fixed dt: CFL 0.4 on the fine level, an integer number of steps to t = 1/2
-        nsteps = int(math.ceil(0.5 / (0.4 * dx1 / (1.0 + math.sqrt(1.4 / 0.8)))))
+        # fixed dt: CFL 0.4 on the fine level, an even number of fine steps to t = 1/2; the
+        # crossover advance takes half as many level-0 steps of twice the length
+        nsteps = 2 * int(math.ceil(0.25 / (0.4 * dx1 / (1.0 + math.sqrt(1.4 / 0.8)))))
         dt = 0.5 / nsteps
         U, T = oracle.block_state(bc)
-        U, T, t, _, _ = oracle.step_blocks(bc, U, T, nsteps, dt_fixed=dt)
+        if crossover:
+            U, T, t, _, _ = oracle.step_blocks(bc, U, T, nsteps // 2, dt_fixed=2 * dt,
+                                               crossover=True)
+        else:
+            U, T, t, _, _ = oracle.step_blocks(bc, U, T, nsteps, dt_fixed=dt)
         assert t[0] == pytest.approx(0.5, rel=1e-14)
         b0 = bc.blocks[0]
         rho = _block_data(U, b0)[0]                     # level 0 = effective field, restricted
@@ -189,5 +196,6 @@ def test_entropy_wave_through_refined_band_converges(oracle):
     # first order: the coupling injects piecewise-constant coarse values into the ring and
     # averages ring children with fine ones, an O(dx) error at the band's inflow edge
     ratios = [a / b for a, b in zip(errs[:-1], errs[1:])]
+    print(f"crossover={crossover}: L1 errors {errs}")
     assert min(ratios) > 1.5 and ratios[-1] > 1.8, errs
     assert errs[-1] < 1e-2, errs
