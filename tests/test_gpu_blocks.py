@@ -344,3 +344,18 @@ def test_entropy_wave_refined_band_vs_oracle(crossover):
     c = _entropy_wave(64)
     c.dt_fixed = 0.5 / 372
     _cmp_blocks(c, 60 if crossover else 120, crossover=crossover)
+
+
+def test_transposed_hierarchy_vs_oracle():
+    """An asymmetric 3-level hierarchy and its transpose: each against the oracle, and the
+    GPU results transposes of each other."""
+    from test_oracle_amr_symmetry import _asymmetric_case, _transposed, _block_data
+    c = _asymmetric_case()
+    ct = _transposed(c)
+    Ug, _ = _cmp_blocks(c, 12)
+    Ugt, _ = _cmp_blocks(ct, 12)
+    for b, bt in zip(c.blocks, ct.blocks):
+        A = _block_data(Ug, b)
+        Bt = _block_data(Ugt, bt).transpose(0, 2, 1)[[0, 2, 1, 3, 4]]
+        for f in range(5):
+            assert np.max(np.abs(A[f] - Bt[f])) <= 1e-12 * np.max(np.abs(Ug[f])), f

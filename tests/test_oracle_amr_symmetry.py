@@ -112,7 +112,8 @@ def _transposed(bc):
                      W=np.concatenate(parts, axis=1), cfl=bc.cfl)
 
 
-def test_transposed_hierarchy_gives_transposed_result(oracle):
+def _asymmetric_case():
+    """A wrinkled-band 3-level hierarchy on a 128 x 64 base, with no symmetry."""
     _, geo = build_hierarchy(128, 64, DX0, 3, (1.0, 0.7), blk0=32, seed=8, margin=6)
     recs = [(0, lev, i0, j0, nx, ny) for (lev, i0, j0, nx, ny) in geo]
 
@@ -128,8 +129,12 @@ def test_transposed_hierarchy_gives_transposed_result(oracle):
     dom = Domain(nx=128, ny=64, dx=DX0, dy=DX0,
                  bc=[BC_ZEROGRAD, BC_SLIPWALL, BC_SLIPWALL, BC_ZEROGRAD], nlevels=3,
                  gamma=1.2, R=1.0, Q=50.0, Ea=24.0, k=30.0)
-    bc = BlockCase(name="amr", model=MODEL_ONESTEP, domains=[dom], blocks=make_blocks(recs),
-                   W=_onestep_state(recs, fn), cfl=0.5)
+    return BlockCase(name="asymmetric", model=MODEL_ONESTEP, domains=[dom],
+                     blocks=make_blocks(recs), W=_onestep_state(recs, fn), cfl=0.5)
+
+
+def test_transposed_hierarchy_gives_transposed_result(oracle):
+    bc = _asymmetric_case()
     assert (bc.blocks["level"] == 2).any()
     bt = _transposed(bc)
     U, T = oracle.block_state(bc)
