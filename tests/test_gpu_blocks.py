@@ -320,12 +320,13 @@ def test_amr_domain_alone_equals_in_pair_bitwise():
     assert np.array_equal(Up[:, a.pool_cells:], Ub) and tp[1] == tb[0] and tp[0] != tp[1]
 
 
-def test_mirror_hierarchy_vs_oracle():
+@pytest.mark.parametrize("crossover", [False, True])
+def test_mirror_hierarchy_vs_oracle(crossover):
     """The mirror-pair hierarchy of the oracle's symmetry pin: parity, and the GPU result
     itself mirror-symmetric."""
     from test_oracle_amr_symmetry import _mirror_case, _block_data
     c = _mirror_case()
-    Ug, _ = _cmp_blocks(c, 20)
+    Ug, _ = _cmp_blocks(c, 6 if crossover else 20, crossover=crossover)
     lw0 = c.domains[0].nx
     for b in c.blocks:
         lev = int(b["level"])

@@ -3,11 +3,12 @@ coarser level's value, covered coarse cells the mean of their four children) tha
 hold without a closed form of the coupled solution:
 
 * mirror symmetry: a hierarchy and a state that are mirror images about the domain's
-  vertical mid-line (u odd) stay mirror images; an off-by-one parent index, a ring
+  vertical mid-line (u odd) stay mirror images, in the synchronous and the crossover
+  advance; an off-by-one parent index, a ring
   that is wider on one side, or a restriction that reads the wrong child breaks it;
 * transposition: swapping x and y in the table (i0 <-> j0, nx <-> ny), the data of
   every block and the velocity components transposes the result of an asymmetric
-  3-level hierarchy; an x/y mix-up in the coupling breaks it;
+  3-level hierarchy (both advances); an x/y mix-up in the coupling breaks it;
 * convergence: a density wave advected at constant velocity and pressure through a
   refined band returns the exact translated profile as the grid is refined, at first
   order or better in the L1 norm over the whole domain, in the synchronous and the
@@ -70,11 +71,12 @@ def _mirror_case():
                      W=_onestep_state(recs, fn), cfl=0.5)
 
 
-def test_mirror_symmetric_hierarchy_stays_symmetric(oracle):
+@pytest.mark.parametrize("crossover", [False, True])
+def test_mirror_symmetric_hierarchy_stays_symmetric(oracle, crossover):
     bc = _mirror_case()
     blocks = bc.blocks
     U0, T0 = oracle.block_state(bc)
-    U, T, _, _, _ = oracle.step_blocks(bc, U0, T0, 20)
+    U, T, _, _, _ = oracle.step_blocks(bc, U0, T0, 6 if crossover else 20, crossover=crossover)
     flags = oracle.ring_flags(bc)
     assert flags.any()
     lw0 = bc.domains[0].nx
@@ -133,14 +135,16 @@ def _asymmetric_case():
                      blocks=make_blocks(recs), W=_onestep_state(recs, fn), cfl=0.5)
 
 
-def test_transposed_hierarchy_gives_transposed_result(oracle):
+@pytest.mark.parametrize("crossover", [False, True])
+def test_transposed_hierarchy_gives_transposed_result(oracle, crossover):
     bc = _asymmetric_case()
     assert (bc.blocks["level"] == 2).any()
     bt = _transposed(bc)
+    n = 4 if crossover else 12
     U, T = oracle.block_state(bc)
     Ut, Tt = oracle.block_state(bt)
-    U, T, t, _, _ = oracle.step_blocks(bc, U, T, 12)
-    Ut, Tt, tt, _, _ = oracle.step_blocks(bt, Ut, Tt, 12)
+    U, T, t, _, _ = oracle.step_blocks(bc, U, T, n, crossover=crossover)
+    Ut, Tt, tt, _, _ = oracle.step_blocks(bt, Ut, Tt, n, crossover=crossover)
     assert tt[0] == pytest.approx(t[0], rel=1e-14)   # dt's two direction terms add in swapped order
     for b, c in zip(bc.blocks, bt.blocks):
         A = _block_data(U, b)
