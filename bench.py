@@ -148,6 +148,9 @@ def main():
     ap.add_argument("--no-regrid", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--paper-shape", action="store_true",
+                    help="also time the uniform 9-species path on a 4000 x 1000 grid, the shape "
+                         "of the paper's single-GPU core-solver run (context only)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -440,6 +443,39 @@ def main():
         return adjoint
     adjoint = None if args.no_adjoint else optional("adjoint", _adjoint)
 
+    # ------------------------------------------------------------ uniform grid, paper's shape
+    def _paper_shape():
+        from cases.amr import detailed_front_case
+        pc = detailed_front_case(nx=4000, ny=1000, mech=case.mech)
+        pctx = janc.Context(janc.DETAILED, pc.mech)
+        pph = janc.physics_of(pc)
+        pg = janc.grid_of(pc)
+        ptm = janc.time_of(pc)
+        Wp = torch.tensor(pc.W, dtype=torch.float64, device=dev)
+        Up, Tp = pctx.init_state(pph, Wp)
+        del Wp
+        tp = torch.zeros(1, dtype=torch.float64, device=dev)
+        pctx.step(pg, pph, ptm, Up, Tp, 2, tp)
+        psteps = 10
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        pctx.step(pg, pph, ptm, Up, Tp, psteps, tp)
+        e1.record()
+        torch.cuda.synchronize()
+        ps = e0.elapsed_time(e1) / 1e3
+        pctx.sync_status()
+        ncell = pc.nx * pc.ny
+        res = {"workload": f"uniform {pc.nx}x{pc.ny}, synthetic 9 species / 19 reactions, "
+                           f"CFL {pc.cfl}", "steps": psteps, "ms_per_step": 1e3 * ps / psteps,
+               "steps_per_s": psteps / ps, "cell_stage_per_s": ncell * 3 * psteps / ps,
+               "paper_context": "A100, H2-O2 9 species / 19 reactions, 4000x1000: 5.0 step/s"}
+        log(f"[bench] uniform {pc.nx}x{pc.ny} 9-species: {res['ms_per_step']:.3f} ms/step, "
+            f"{res['steps_per_s']:.1f} step/s, {res['cell_stage_per_s']:.3e} cell-stage/s")
+        pctx.close()
+        return res
+    paper_shape = optional("paper_shape", _paper_shape) if args.paper_shape else None
+
     def _cpu():
         cpu = None
         log(f"[bench] CPU oracle baseline ({args.cpu_steps} step)")
@@ -494,6 +530,7 @@ def main():
         "regrid": regrid,
         "ensemble": ensemble,
         "adjoint": adjoint,
+        **({"paper_shape": paper_shape} if paper_shape is not None else {}),
         "cpu_baseline": cpu,
         "context": "paper (A100, real H2-O2 mechanism, 2.76 M cells incl. invalid blocks): "
                    "0.18 s/step synchronous AMR, about 4.6e7 cell-stage/s; not the same "
