@@ -150,3 +150,37 @@ def two_range_mechanism(mech: Mechanism, t_mid: float = 1800.0, eps: float = 0.0
     out.nasa_high = high
     out.t_mid = np.full(mech.ns, Tm)
     return out
+
+
+def complete_mechanism(base: Mechanism = None, A_cgs: float = 1e13) -> Mechanism:
+    """Every element-balanced exchange and recombination among the 8 reacting species of
+    `base` (19 + 11 = 30 reversible reactions, third body M with unit efficiencies) on the
+    same species and NASA-7 data, with one fast temperature-independent rate A = A_cgs.
+
+    Every species is linked to every other by some channel, so a constant-volume reactor
+    relaxes to the Gibbs equilibrium of the mixture within a few thousand short steps (the
+    seeded 19-reaction set stalls in a partial equilibrium). The equilibrium itself does
+    not depend on the rates."""
+    if base is None:
+        base = synthetic_mechanism()
+    ns = base.ns
+    exch, recomb = _candidates(ns - 1)
+    rx = exch + recomb
+    nr = len(rx)
+    nu_f = np.zeros((nr, ns), dtype=np.int32)
+    nu_b = np.zeros((nr, ns), dtype=np.int32)
+    for i, (r, p) in enumerate(rx):
+        for s in r:
+            nu_f[i, s] += 1
+        for s in p:
+            nu_b[i, s] += 1
+    has_tb = np.array([0] * len(exch) + [1] * len(recomb), dtype=np.int32)
+    tb = np.zeros((nr, ns))
+    tb[has_tb == 1] = 1.0
+    order = nu_f.sum(axis=1) + has_tb
+    a_cgs = np.full(nr, float(A_cgs))
+    return Mechanism(species=list(base.species), elements=list(base.elements),
+                     comp=base.comp.copy(), M=base.M.copy(), nasa=base.nasa.copy(),
+                     A=a_cgs * (1e-6) ** (order - 1), b=np.zeros(nr), Ea=np.zeros(nr),
+                     nu_f=nu_f, nu_b=nu_b, tb=tb, has_tb=has_tb,
+                     reversible=np.ones(nr, dtype=np.int32), A_cgs=a_cgs, Ea_kcal=np.zeros(nr))

@@ -14,7 +14,7 @@ import pytest
 
 from cases import (Case, synthetic_mechanism, detonation_tube_case, MODEL_ONESTEP,
                    MODEL_DETAILED, BC_PERIODIC, BC_ZEROGRAD)
-from cases.mechanism import Mechanism, fresh_mass_fractions
+from cases.mechanism import Mechanism, fresh_mass_fractions, complete_mechanism
 from cases.amr import detailed_front_case
 import refsol
 
@@ -210,6 +210,43 @@ def test_detailed_equilibrium_consistency(oracle, mech):
     # fixed point of the point-implicit map
     out = oracle.point_implicit(mech, rho, Teq, rhoY, 1e-6)
     assert np.max(np.abs(out - rhoY)) <= 1e-9 * rho
+
+
+def _reactor_start(mech, start):
+    """Initial 0-D state: the fresh A2/B2/C2 mixture at 1500 K, or the same element
+    amounts as free atoms A, B (with C2) at 600 K; 20 atm."""
+    if start == "fresh-1500K":
+        return 1500.0, fresh_mass_fractions(mech)
+    Y = np.zeros(mech.ns)
+    Y[mech.species.index("A")], Y[mech.species.index("B")] = 0.03, 0.23
+    Y[mech.species.index("C2")] = 0.74
+    return 600.0, Y
+
+
+@pytest.mark.parametrize("start", ["atoms-600K", "fresh-1500K"])
+def test_adiabatic_reactor_relaxes_to_gibbs_equilibrium(oracle, start):
+    """Constant-volume adiabatic reactor with the complete-channel mechanism: the long-time
+    limit of the point-implicit steps (Eq. 4.12-4.13) with the Newton temperature is the
+    independent Gibbs equilibrium of the same thermo at the same rho, e and element totals
+    (element potentials, scipy): T to 1e-9, mole fractions to 1e-7. From free atoms the
+    recombination releases heat (an ignition, T 600 -> 921 K); from the fresh mixture at
+    1500 K the molecules dissociate and T falls."""
+    mech = complete_mechanism()
+    T0, Y = _reactor_start(mech, start)
+    c = _zero_d_case(mech, 20 * 101325.0, T0, Y)
+    U, T = oracle.case_state(c)
+    rho, e = U[0, 0, 0], U[3, 0, 0] / U[0, 0, 0]
+    X0 = np.r_[U[4:, 0, 0], rho - U[4:, 0, 0].sum()] / mech.M
+    b = mech.comp.T.astype(float) @ X0
+    Teq, Xeq = refsol.equilibrium_T(mech, rho, e, b)
+    for dt in (1e-10, 1e-9, 1e-8, 1e-7):
+        U, T, _, _, _ = oracle.step(c, U, T, 200, dt_fixed=dt)
+    X = np.r_[U[4:, 0, 0], rho - U[4:, 0, 0].sum()] / mech.M
+    assert T[0, 0] == pytest.approx(Teq, rel=1e-9)
+    assert np.max(np.abs(X - Xeq)) <= 1e-7 * X.sum()
+    assert abs(Teq - T0) > 250.0                 # the reactor did change state
+    if start == "atoms-600K":
+        assert Teq > T0
 
 
 # ------------------------------------------------------------------ conservation (P4)
