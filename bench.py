@@ -100,6 +100,22 @@ def optional(name, fn):
         return {"error": f"{type(e).__name__}: {e}"}
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host that runs the oracle."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+            else None}
+
+
 def cpu_baseline(case, steps, target_s=10.0, max_steps=20):
     """The oracle on the same workload: `steps` steps, extended to about target_s of work."""
     import oracle
@@ -116,7 +132,7 @@ def cpu_baseline(case, steps, target_s=10.0, max_steps=20):
             steps += more
     cells = case.valid_cells()
     out = {"value": cells * 3 * steps / el, "unit": "cell-stage/s",
-           "cores": oracle.max_threads(), "kind": "oracle",
+           "cores": oracle.max_threads(), "kind": "oracle", "host": host_cpu(),
            "sample": f"{steps} step(s) of the same {len(case.blocks)}-block AMR workload "
                      f"({cells} cells), OpenMP over all host threads, {el:.1f} s"}
     # the same oracle on one host thread, one step
@@ -214,12 +230,28 @@ def main():
     # ------------------------------------------------------------ fused batched form
     log(f"[bench] fused batched step: {len(case.blocks)} blocks, {cells} cells, "
         f"{args.warmup} warm-up + {args.steps} timed steps")
+    # default launch shape (16 x 16 tiles, XCD-contiguous tile runs), then the shape the
+    # autotuner picks on the workload's own state; the headline is the tuned plan
+    dplan = ctx.plan(domains, case.blocks, case.pool_cells, janc.PLAN_DEFAULT)
+    d_s, _, _ = timed_run(dplan, args.steps, args.warmup)
+    dplan.close()
+    default_value = cells * 3 * args.steps / d_s
+    log(f"[bench] default shape: {1e3 * d_s / args.steps:.3f} ms/step, {default_value:.4e} cell-stage/s")
     plan = ctx.plan(domains, case.blocks, case.pool_cells, janc.PLAN_DEFAULT)
+    U0, T0, _ = fresh_state()
+    choice, cand_ms = plan.autotune(tm, U0, T0, reps=5)
+    del U0, T0
+    log(f"[bench] autotuner: tile width {choice[0]}, {'linear' if choice[1] else 'XCD-contiguous'} "
+        f"order; candidates (ms per first-stage launch) "
+        + ", ".join(f"{w}/{'lin' if l else 'xcd'} {v:.3f}" for (w, l), v in cand_ms.items()))
     sim_sync = []
     gpu_s, wall_s, (U, T, t) = timed_run(plan, args.steps, args.warmup, sim_sync)
     value = cells * 3 * args.steps / gpu_s
     ms_step = 1e3 * gpu_s / args.steps
     log(f"[bench] {ms_step:.3f} ms/step, {value:.4e} cell-stage/s (wall {wall_s:.3f} s)")
+    autotune = {"tile_width": choice[0], "order": "linear" if choice[1] else "xcd-contiguous",
+                "candidates_ms": {f"{w}/{'linear' if l else 'xcd'}": v for (w, l), v in cand_ms.items()},
+                "default_shape_value": default_value, "gain_over_default": value / default_value}
 
     # ------------------------------------------------------------ per-kernel timing (HIP events)
     stage_ms, chem_ms, restr_ms, ring_ms = [], [], [], []
@@ -258,6 +290,19 @@ def main():
         log(f"[bench] per-block form {per_block['ms_per_step']:.3f} ms/step "
             f"-> fused speed-up {value / pb_value:.2f}x")
         pplan.close()
+        # the paper's structure: one batched launch per refinement level and stage
+        # (graph-captured like the fused form)
+        lplan = ctx.plan(domains, case.blocks, case.pool_cells, janc.PLAN_PER_LEVEL)
+        pl_s, _, _ = timed_run(lplan, args.steps, args.warmup)
+        pl_value = cells * 3 * args.steps / pl_s
+        per_block["per_level"] = {"value": pl_value, "unit": "cell-stage/s",
+                                  "ms_per_step": 1e3 * pl_s / args.steps, "steps": args.steps,
+                                  "speedup_of_fused": value / pl_value,
+                                  "form": "one launch per refinement level and RK stage, "
+                                          "graph-captured (per-level batching, Alg. 2)"}
+        log(f"[bench] per-level form {per_block['per_level']['ms_per_step']:.3f} ms/step "
+            f"-> fused speed-up {value / pl_value:.2f}x")
+        lplan.close()
         return per_block
     per_block = None if args.no_per_block else optional("per_block", _per_block)
 
@@ -525,6 +570,7 @@ def main():
         },
         "kernels_ms": {"stage": stage_avg, "chemistry": float(np.mean(chem_ms)),
                        "restriction": float(np.mean(restr_ms)), "ring": float(np.mean(ring_ms))},
+        "autotune": autotune,
         "per_block": per_block,
         "crossover": crossover,
         "regrid": regrid,

@@ -180,7 +180,11 @@ enum {
     JANC_PLAN_DEFAULT = 0,
     JANC_PLAN_PER_BLOCK = 1,   /* one launch per block and stage (comparison form) */
     JANC_PLAN_NO_GRAPH = 2,    /* launch kernels directly instead of a captured hipGraph */
-    JANC_PLAN_CROSSOVER = 4    /* crossover advance (Fig. 2a, Alg. 2) instead of the synchronous one */
+    JANC_PLAN_CROSSOVER = 4,   /* crossover advance (Fig. 2a, Alg. 2) instead of the synchronous one */
+    JANC_PLAN_PER_LEVEL = 8,   /* one stage launch per refinement level (comparison form: the
+                                  paper's per-level batching of equal-shape blocks, Alg. 2) */
+    JANC_PLAN_AUTOTUNE = 16    /* the first janc_step_blocks call runs janc_plan_autotune on its
+                                  input state (5 timed launches per candidate) before stepping */
 };
 
 /* Validate a block table and build its device work lists (blocks, level maps,
@@ -199,6 +203,25 @@ janc_status janc_plan_stats(const janc_plan *plan, long long *out);
 /* Per-plan tile shape (autotuner hook): 0 = automatic, else tile width in cells
  * for 2-D blocks (16 or 32 or 64; height = 256 / width). Synchronous. */
 janc_status janc_plan_set_tile(janc_plan *plan, int tile_width);
+
+/* Tile width (as janc_plan_set_tile) and the order in which workgroups take tiles:
+ * linear = 1: workgroup b takes tile b; linear = 0 (default): the workgroups dealt to
+ * each of the 8 XCDs take one contiguous run of tiles, so that neighbouring tiles,
+ * whose halos overlap, are read through the same L2. Results do not depend on either. */
+janc_status janc_plan_set_schedule(janc_plan *plan, int tile_width, int linear);
+
+/* Autotuner of the batched stage launch (systems pattern, not in the paper): times each
+ * candidate -- 2-D tile width 16, 32, 64 (16x16, 32x8, 64x4 cells) times the two
+ * workgroup orders of janc_plan_set_schedule; 1-D-only plans: the two orders -- over
+ * `reps` (1..1000) first-stage launches on the state U, T (device, read only; only the
+ * plan's workspaces are written), with HIP events on `stream`, and keeps the fastest in
+ * the plan (synchronous on the host). choice (host [2], may be NULL) receives the tile
+ * width and the order; ms (host [6], may be NULL) the median launch time of each
+ * candidate in the order (16, XCD), (16, linear), (32, XCD), (32, linear), (64, XCD),
+ * (64, linear), -1 where not timed. Every candidate gives bitwise the same results. */
+janc_status janc_plan_autotune(janc_ctx *ctx, janc_plan *plan, const janc_time *time,
+                               const double *U, const double *T, int reps, int *choice,
+                               double *ms, void *stream);
 
 /* nsteps steps over a block table (Alg. 2 and Alg. 3 per stage): per domain dt;
  * per (domain, level) alpha; after each step coarse cells under finer blocks

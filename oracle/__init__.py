@@ -54,12 +54,15 @@ class OracleError(RuntimeError):
 
 
 def lib():
+    """The oracle library. JANC_ORACLE_VARIANT=fma selects the build with fused
+    multiply-add contraction, used only to measure round-off floors."""
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liboracle.so")
+        variant = os.environ.get("JANC_ORACLE_VARIANT") or None
+        path = _build.lib_path(variant)
         src = os.path.join(_HERE, "janc_oracle.cpp")
         if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
-            _build.build()
+            _build.build(variant=variant)
         _LIB = C.CDLL(path)
         _LIB.oracle_weno5.restype = D
         _LIB.oracle_max_threads.restype = I

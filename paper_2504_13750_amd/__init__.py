@@ -36,7 +36,9 @@ from ._lib import LibraryMissing
 
 CPG, ONESTEP, DETAILED = 0, 1, 2
 BC_PERIODIC, BC_ZEROGRAD, BC_SLIPWALL, BC_DIRICHLET = 0, 1, 2, 3
-PLAN_DEFAULT, PLAN_PER_BLOCK, PLAN_NO_GRAPH, PLAN_CROSSOVER = 0, 1, 2, 4
+PLAN_DEFAULT, PLAN_PER_BLOCK, PLAN_NO_GRAPH, PLAN_CROSSOVER, PLAN_PER_LEVEL = 0, 1, 2, 4, 8
+PLAN_AUTOTUNE = 16
+AUTOTUNE_CANDIDATES = [(16, 0), (16, 1), (32, 0), (32, 1), (64, 0), (64, 1)]
 SPLIT_LIE, SPLIT_STRANG = 0, 1
 JAC_FROZEN_T, JAC_FULL = 0, 1
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONFINITE", -5: "ENEWTON",
@@ -160,6 +162,20 @@ class Plan:
     def set_tile(self, width):
         self.ctx._check(L.lib().janc_plan_set_tile(self.h, int(width)))
 
+    def set_schedule(self, width, linear):
+        self.ctx._check(L.lib().janc_plan_set_schedule(self.h, int(width), int(linear)))
+
+    def autotune(self, time, U, T, reps=5, stream=None):
+        """janc_plan_autotune: returns ((tile width, linear order), {candidate: ms})."""
+        choice = (C.c_int * 2)()
+        ms = (C.c_double * 6)()
+        self.ctx._check(L.lib().janc_plan_autotune(
+            self.ctx.h, self.h, C.byref(time), _dptr(U, self.ctx.nfields * self.pool_cells, "U"),
+            _dptr(T, self.pool_cells, "T"), int(reps), choice, ms,
+            C.c_void_p(_stream_handle(stream))))
+        times = {AUTOTUNE_CANDIDATES[q]: ms[q] for q in range(6) if ms[q] >= 0.0}
+        return (choice[0], choice[1]), times
+
     def stats(self):
         """dict(cells, ring_cells, blocks, tiles) of the plan."""
         out = (C.c_longlong * 4)()
@@ -219,6 +235,9 @@ class Context:
     def init_state(self, phys, W, stream=None):
         """Primitive W [nfields, ...] (device) -> (U, T) (new device tensors)."""
         torch = _torch()
+        if W.dim() < 2 or W.shape[0] != self.nfields:
+            raise ValueError(f"W must have {self.nfields} fields in its leading dimension, "
+                             f"got shape {tuple(W.shape)}")
         n = W[0].numel()
         U = torch.empty_like(W)
         T = torch.empty(W.shape[1:], dtype=torch.float64, device=W.device)
@@ -229,6 +248,8 @@ class Context:
 
     def step(self, grid, phys, time, U, T, nsteps, t, dt_log=None, stream=None):
         n = grid.nx * grid.ny
+        if dt_log is not None and dt_log.numel() < int(nsteps):
+            raise ValueError(f"dt_log has {dt_log.numel()} elements, the call writes {int(nsteps)}")
         self._check(L.lib().janc_step(self.h, C.byref(grid), C.byref(phys), C.byref(time),
                                       _dptr(U, self.nfields * n, "U"), _dptr(T, n, "T"),
                                       int(nsteps), _dptr(t, 1, "t"),

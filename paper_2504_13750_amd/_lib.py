@@ -64,6 +64,9 @@ EXPORTS = {
                              C.POINTER(VP)]),
     "janc_plan_destroy": (None, [VP]),
     "janc_plan_set_tile": (I, [VP, I]),
+    "janc_plan_set_schedule": (I, [VP, I, I]),
+    "janc_plan_autotune": (I, [VP, VP, C.POINTER(janc_time), VP, VP, I, C.POINTER(I),
+                               C.POINTER(C.c_double), VP]),
     "janc_plan_stats": (I, [VP, C.POINTER(C.c_longlong)]),
     "janc_step_blocks": (I, [VP, VP, C.POINTER(janc_time), VP, VP, I, VP, VP]),
     "janc_profile_step": (I, [VP, VP, C.POINTER(janc_time), VP, VP, VP, C.POINTER(C.c_double),

@@ -61,6 +61,8 @@ struct janc_plan {
     long long pool = 0;
     int nunits = 0;
     int tile_w = 16;
+    int linear_sched = 0;         // 1: workgroup b takes tile b; 0: XCD-contiguous tile runs
+    bool tuned = false;           // janc_plan_autotune has chosen tile_w and linear_sched
     int kind_mask = 0;            // bit 0: 2-D tiles present, bit 1: 1-D tiles present
     int maxlev = 0;
     std::vector<DevDomain> hdom;
@@ -92,6 +94,7 @@ struct janc_plan {
     GraphKey gkey{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    hipEvent_t gdone = nullptr;    // recorded after the last replay of the graph
 };
 
 namespace {
@@ -149,8 +152,10 @@ template <class T> janc_status upload(janc_ctx* c, T** p, const std::vector<T>& 
 
 void plan_free(janc_plan* p) {
     if (!p) return;
+    if (p->gdone) hipEventSynchronize(p->gdone);
     if (p->gexec) hipGraphExecDestroy(p->gexec);
     if (p->graph) hipGraphDestroy(p->graph);
+    if (p->gdone) hipEventDestroy(p->gdone);
     void* ptrs[] = {p->ddom, p->dblk, p->dmap, p->dtiles, p->ddir, p->dred, p->ddt, p->dstep,
                     p->dfine, p->dring, p->U1, p->U2, p->T1, p->T2};
     for (void* q : ptrs)
@@ -230,10 +235,13 @@ janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, con
         return fail(c, JANC_EINVAL, "empty block table");
     std::unique_ptr<janc_plan, void (*)(janc_plan*)> P(new janc_plan(), plan_free);
     P->ctx = c;
-    if (flags & ~(JANC_PLAN_PER_BLOCK | JANC_PLAN_NO_GRAPH | JANC_PLAN_CROSSOVER))
+    if (flags & ~(JANC_PLAN_PER_BLOCK | JANC_PLAN_NO_GRAPH | JANC_PLAN_CROSSOVER | JANC_PLAN_PER_LEVEL |
+                  JANC_PLAN_AUTOTUNE))
         return fail(c, JANC_EINVAL, "unknown plan flags");
     if ((flags & JANC_PLAN_PER_BLOCK) && (flags & JANC_PLAN_CROSSOVER))
         return fail(c, JANC_EINVAL, "the crossover advance has no per-block form");
+    if ((flags & JANC_PLAN_PER_LEVEL) && (flags & (JANC_PLAN_PER_BLOCK | JANC_PLAN_CROSSOVER)))
+        return fail(c, JANC_EINVAL, "the per-level form is a form of the synchronous batched advance");
     P->flags = flags;
     P->ndom = nd;
     P->pool = pool;
@@ -508,6 +516,7 @@ StageArgs base_args(janc_plan* P, const janc_time* tm, double* U, double* T, dou
     a.strang = (tm->split == JANC_SPLIT_STRANG && P->ctx->model == DETAILED) ? 1 : 0;
     a.full_jac = (tm->jac == JANC_JAC_FULL && P->ctx->model == DETAILED) ? 1 : 0;
     a.status = P->ctx->dstatus;
+    a.linear_sched = P->linear_sched;
     if (P->flags & JANC_PLAN_CROSSOVER) {
         a.cross = 1;
         a.xlevels = P->maxlev + 1;
@@ -644,6 +653,9 @@ hipError_t enqueue_step(janc_plan* P, const StageArgs& base, double* U, double* 
         if (P->flags & JANC_PLAN_PER_BLOCK) {
             for (int id = 0; id < P->nblk && e == hipSuccess; ++id)
                 e = launch_stage(model, ns, P->kind_mask, P->tile_w, a, P->tile_first[id], P->tile_count[id], s);
+        } else if (P->flags & JANC_PLAN_PER_LEVEL) {
+            for (int l = 0; l <= P->maxlev && e == hipSuccess; ++l)
+                e = launch_stage(model, ns, P->kind_mask, P->tile_w, a, P->lev_first[l], P->lev_count[l], s);
         } else {
             e = launch_stage(model, ns, P->kind_mask, P->tile_w, a, 0, a.ntiles, s);
         }
@@ -663,7 +675,10 @@ hipError_t enqueue_step(janc_plan* P, const StageArgs& base, double* U, double* 
     return e;
 }
 
+// The executable graph may still be replaying on the stream of an earlier call:
+// wait for its last replay before destroying it.
 void drop_graph(janc_plan* P) {
+    if (P->gexec && P->gdone) hipEventSynchronize(P->gdone);
     if (P->gexec) hipGraphExecDestroy(P->gexec);
     if (P->graph) hipGraphDestroy(P->graph);
     P->gexec = nullptr;
@@ -671,11 +686,110 @@ void drop_graph(janc_plan* P) {
     P->have_graph = false;
 }
 
+// Autotuner of the stage launch: each candidate (2-D tile width 16, 32 or 64 --
+// 16 x 16, 32 x 8, 64 x 4 cells -- and the tile order of the workgroups) is timed
+// with HIP events over `reps` first-stage launches of the plan on the state (U, T);
+// the fastest is kept in the plan. Only the plan's own workspaces are written (the
+// first stage's output goes to the stage buffer), and every candidate computes the
+// same result bitwise, so the choice changes speed only.
+janc_status autotune(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U, double* T, int reps,
+                     double* ms_out, hipStream_t s) {
+    HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    struct Cand { int w, lin; };
+    std::vector<Cand> cands;
+    const int widths[3] = {16, 32, 64};
+    for (int wi = 0; wi < 3; ++wi) {
+        if (!(P->kind_mask & 1) && wi > 0) break;   // 1-D tiles only: the width does not apply
+        for (int lin = 0; lin < 2; ++lin) cands.push_back({widths[wi], lin});
+    }
+    const int w0 = P->tile_w, l0 = P->linear_sched;
+    hipEvent_t ev[2];
+    HIPCHK(c, hipEventCreate(&ev[0]), "hipEventCreate");
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        hipEventDestroy(ev[0]);
+        return fail(c, JANC_EHIP, "hipEventCreate");
+    }
+    double best = INFINITY;
+    int bw = w0, bl = l0;
+    hipError_t e = hipSuccess;
+    janc_status st = JANC_OK;
+    for (size_t k = 0; k < cands.size() && e == hipSuccess && !st; ++k) {
+        if (cands[k].w != P->tile_w) {
+            P->tile_w = cands[k].w;
+            st = build_tiles(c, P);
+            if (st) break;
+        }
+        P->linear_sched = cands[k].lin;
+        StageArgs base = base_args(P, tm, U, T, nullptr, nullptr, 0);
+        base.cross = 0;   // timed as one synchronous launch over every tile
+        base.red = Reduce{P->dred, P->red_stride, P->nunits, P->ndom, 0};
+        base.strang = 0;
+        base.tm.t_end = 0.0;   // no clipping: t is not read
+        StageArgs a0 = base;
+        a0.Uin = U;
+        a0.Tin = T;
+        a0.Tout = P->T1;   // the entry T solve writes the workspace, not the caller's T
+        e = launch_zero_int(P->dstep, s);
+        if (e == hipSuccess) e = launch_clear_reduce(base.red, -1, s);
+        if (e == hipSuccess) e = launch_init(c->model, c->ns, P->tile_w, a0, s);
+        StageArgs a = base;
+        a.stage = 1;
+        a.Uin = U;
+        a.Tin = P->T1;
+        a.Uout = P->U1;
+        a.Tout = P->T2;
+        a.reduce_out = 1;
+        std::vector<float> times;
+        for (int r = 0; r <= reps && e == hipSuccess; ++r) {   // r = 0: warm-up
+            e = hipEventRecord(ev[0], s);
+            if (e == hipSuccess) e = launch_stage(c->model, c->ns, P->kind_mask, P->tile_w, a, 0, a.ntiles, s);
+            if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            float f = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&f, ev[0], ev[1]);
+            if (r > 0) times.push_back(f);
+        }
+        if (e != hipSuccess) break;
+        std::sort(times.begin(), times.end());
+        const double med = times.empty() ? INFINITY : times[times.size() / 2];
+        if (ms_out) ms_out[k] = med;
+        if (med < best) {
+            best = med;
+            bw = cands[k].w;
+            bl = cands[k].lin;
+        }
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (ms_out)
+        for (size_t k = cands.size(); k < 6; ++k) ms_out[k] = -1.0;
+    // keep the fastest (or restore the previous choice after a failure)
+    if (e != hipSuccess || st) {
+        bw = w0;
+        bl = l0;
+    }
+    P->linear_sched = bl;
+    if (P->tile_w != bw) {
+        P->tile_w = bw;
+        janc_status st2 = build_tiles(c, P);
+        if (!st) st = st2;
+    }
+    drop_graph(P);
+    if (e != hipSuccess) return hipfail(c, e, "autotune");
+    if (st) return st;
+    P->tuned = true;
+    return JANC_OK;
+}
+
 // Call entry (T re-solved from U, maxima for the first stage), then nsteps
 // steps: replayed from a captured hipGraph of one step, or launched directly.
 janc_status run_steps(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U, double* T,
                       int nsteps, double* t, double* dt_log, hipStream_t s) {
     HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    if ((P->flags & JANC_PLAN_AUTOTUNE) && !P->tuned && nsteps > 0) {
+        janc_status st = autotune(c, P, tm, U, T, 5, nullptr, s);
+        if (st) return st;
+    }
     const StageArgs base = base_args(P, tm, U, T, t, dt_log, nsteps);
     HIPCHK(c, launch_zero_int(P->dstep, s), "counter launch");
     StageArgs a0 = base;
@@ -700,7 +814,9 @@ janc_status run_steps(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U,
         for (int n = 0; n < nsteps; ++n) HIPCHK(c, enqueue_step(P, base, U, T, s), "step launch");
         return JANC_OK;
     }
-    const GraphKey key{U, T, t, dt_log, nsteps, tm->cfl, tm->dt_fixed, tm->t_end, tm->split, tm->jac};
+    // the step count enters the captured launches only as the bound of dt_log
+    const GraphKey key{U, T, t, dt_log, dt_log ? nsteps : 0, tm->cfl, tm->dt_fixed, tm->t_end,
+                       tm->split, tm->jac};
     if (!P->have_graph || !(P->gkey == key)) {
         drop_graph(P);
         hipStream_t cs;
@@ -721,6 +837,8 @@ janc_status run_steps(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U,
         P->have_graph = true;
     }
     for (int n = 0; n < nsteps; ++n) HIPCHK(c, hipGraphLaunch(P->gexec, s), "hipGraphLaunch");
+    if (!P->gdone) HIPCHK(c, hipEventCreateWithFlags(&P->gdone, hipEventDisableTiming), "hipEventCreate");
+    HIPCHK(c, hipEventRecord(P->gdone, s), "hipEventRecord");
     return JANC_OK;
 }
 
@@ -751,7 +869,6 @@ janc_status uniform_plan(janc_ctx* c, const janc_grid* g, const janc_physics* ph
     c->uphys = *ph;
     return JANC_OK;
 }
-
 
 // ---------------------------------------------------------------- discrete adjoint
 // Forward with checkpoints every k steps (and the probe loss), then segments in
@@ -1291,14 +1408,30 @@ janc_status janc_plan_set_tile(janc_plan* p, int w) {
     if (w == 0) w = 16;
     if (w != 16 && w != 32 && w != 64) return fail(p->ctx, JANC_EINVAL, "tile width must be 16, 32 or 64");
     p->tile_w = w;
-    if (p->have_graph) {
-        hipGraphExecDestroy(p->gexec);
-        hipGraphDestroy(p->graph);
-        p->gexec = nullptr;
-        p->graph = nullptr;
-        p->have_graph = false;
-    }
+    drop_graph(p);
     return build_tiles(p->ctx, p);
+}
+
+janc_status janc_plan_autotune(janc_ctx* c, janc_plan* P, const janc_time* tm, const double* U,
+                               const double* T, int reps, int* choice, double* ms, void* stream) {
+    if (!c || !P || !tm || !U || !T || reps < 1 || reps > 1000) return fail(c, JANC_EINVAL, "bad arguments");
+    if (P->ctx != c) return fail(c, JANC_EINVAL, "plan belongs to another context");
+    if (janc_status st = check_time(c, tm)) return st;
+    janc_status st = autotune(c, P, tm, (double*)U, (double*)T, reps, ms, (hipStream_t)stream);
+    if (st) return st;
+    if (choice) {
+        choice[0] = P->tile_w;
+        choice[1] = P->linear_sched;
+    }
+    return JANC_OK;
+}
+
+janc_status janc_plan_set_schedule(janc_plan* p, int tile_w, int linear) {
+    if (!p) return JANC_EINVAL;
+    if (linear != 0 && linear != 1) return fail(p->ctx, JANC_EINVAL, "linear must be 0 or 1");
+    p->linear_sched = linear;
+    drop_graph(p);
+    return janc_plan_set_tile(p, tile_w);
 }
 
 janc_status janc_step_blocks(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U, double* T,

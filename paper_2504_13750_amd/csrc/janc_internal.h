@@ -126,6 +126,7 @@ struct StageArgs {
     int xlevels;              // levels with reduction slot triples
     unsigned long long* xred; // all levels' slot sets (level l at l * RED_BUFS * red.stride)
     const double* Tbase;      // T of the pool (coarser levels' current state)
+    int linear_sched;         // stage launches: workgroup b takes tile b (else XCD-contiguous runs)
 };
 
 // Layer update: a candidate subregion (layer-`lev` cells) and a fill job.

@@ -23,8 +23,11 @@
 namespace janc {
 
 // ------------------------------------------------------------------ the stage tile
-#ifndef STAGE_SETS
-#define STAGE_SETS 1
+// Conserved components reconstructed per pass between one pair of barriers: their
+// split fluxes go to separate LDS sets, so each thread has STAGE_CPB independent
+// WENO5 chains between the barriers and a stage has 2 ceil(NU / STAGE_CPB) barriers.
+#ifndef STAGE_CPB
+#define STAGE_CPB 2
 #endif
 // Points of a tile: the TX x TY owned positions first (point tid is thread tid's
 // own cell), then the x halo (3 columns each side of every row) and, for 2-D
@@ -42,11 +45,10 @@ struct Geom {
     static constexpr int NIY = TWO ? TX * (TY + 1) : 0; // y interfaces
     static constexpr int NEXT = TY + (TWO ? TX : 0);  // right column / top row interfaces
     // LDS doubles of one set: F+/F- and G+/G-, then the numerical fluxes (sum of the
-    // two one-sided reconstructions) at the x and y interfaces; NSET sets (two: the
-    // next component's fluxes are written while this one is reconstructed, one
-    // barrier per component), then scratch
+    // two one-sided reconstructions) at the x and y interfaces; one set per component
+    // of a pass, then scratch
     static constexpr int SET = 2 * NXS + 2 * NYS + NIX + NIY;
-    static constexpr int NSET = STAGE_SETS;
+    static constexpr int NSET = STAGE_CPB;
     static constexpr int LDS = NSET * SET + 16;
     static constexpr int oFPX = 0, oFMX = NXS, oFPY = 2 * NXS, oFMY = 2 * NXS + NYS;
     static constexpr int oHX = 2 * NXS + 2 * NYS, oHY = oHX + NIX;
@@ -253,26 +255,25 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
             unew[f] = un;
         }
     };
-    if constexpr (G::NSET == 2) {
-        flux(0, smem);
-        __syncthreads();
-    }
+    constexpr int CPB = G::NSET;
 #pragma unroll
-    for (int f = 0; f < NU; ++f) {
-        const double u0 = (stage == 1) ? ur[0][f] : u0q[f % PF];
-        if (f + PF < NU) u0q[f % PF] = ld0 ? a.U0[(size_t)(f + PF) * a.pool + oc] : 0.0;
-        double* S = smem + (G::NSET == 2 ? (f & 1) * G::SET : 0);
-        if constexpr (G::NSET == 2) {
-            recon(S);
-            if (f + 1 < NU) flux(f + 1, smem + ((f + 1) & 1) * G::SET);
-            __syncthreads();
-            update(f, S, u0);
-        } else {
-            flux(f, S);
-            __syncthreads();
-            recon(S);
-            __syncthreads();
-            update(f, S, u0);
+    for (int f0 = 0; f0 < NU; f0 += CPB) {
+#pragma unroll
+        for (int k = 0; k < CPB; ++k)
+            if (f0 + k < NU) flux(f0 + k, smem + k * G::SET);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < CPB; ++k)
+            if (f0 + k < NU) recon(smem + k * G::SET);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < CPB; ++k) {
+            const int f = f0 + k;
+            if (f < NU) {
+                const double u0 = (stage == 1) ? ur[0][f] : u0q[f % PF];
+                if (f + PF < NU) u0q[f % PF] = ld0 ? a.U0[(size_t)(f + PF) * a.pool + oc] : 0.0;
+                update(f, smem + k * G::SET, u0);
+            }
         }
     }
 
@@ -304,7 +305,8 @@ __global__ __launch_bounds__(WG, STAGE_WAVES) void stage_kernel(StageArgs a, int
     constexpr int L2 = Geom<TX, TY>::LDS, L1 = Geom<WG, 1>::LDS;
     __shared__ double smem[(L2 > L1) ? L2 : L1];
     if (blockIdx.x == 0) stage_bookkeeping(a, owner_launch);
-    const Tile tile = a.tiles[first_tile + xcd_chunk(blockIdx.x, gridDim.x)];
+    const Tile tile = a.tiles[first_tile + (a.linear_sched ? (int)blockIdx.x
+                                                           : xcd_chunk(blockIdx.x, gridDim.x))];
     if (HAS1D && tile.kind == 1) {
         if constexpr (HAS1D) stage_tile<M, NU, WG, 1>(a, tile, smem);
     } else {
@@ -513,7 +515,7 @@ __device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, dou
             for (int k = 0; k < NT; ++k) J[k][mm] += dSdT[k] * dTm;
         }
     }
-    // (I - dt J) dU = dt w, Gaussian elimination without pivoting, in place;
+    // (I - dt J) dU = dt w, Gaussian elimination with partial pivoting, in place;
     // w returns the increment of rho Y_1 .. rho Y_{Ns-1}
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
@@ -523,6 +525,28 @@ __device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, dou
     }
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
+        // pivot row: the first row at or below c with the largest |entry| in column c;
+        // rows are exchanged by selects so that the matrix stays in registers
+        int p = c;
+        double amax = fabs(J[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < NT; ++r) {
+            const double ar = fabs(J[r][c]);
+            if (ar > amax) { amax = ar; p = r; }
+        }
+#pragma unroll
+        for (int r = c + 1; r < NT; ++r) {
+            const bool sw = (r == p);
+#pragma unroll
+            for (int q = c; q < NT; ++q) {
+                const double top = J[c][q], row = J[r][q];
+                J[c][q] = sw ? row : top;
+                J[r][q] = sw ? top : row;
+            }
+            const double wt = w[c], wr = w[r];
+            w[c] = sw ? wr : wt;
+            w[r] = sw ? wt : wr;
+        }
         const double piv = J[c][c];
         if (!(fabs(piv) > 0.0) || !isfinite(piv)) st |= STB_NONFINITE;
         const double ip = 1.0 / piv;

@@ -68,6 +68,63 @@ def test_per_block_launches_equal_batched_bitwise():
     assert np.array_equal(Ua, Ub) and np.array_equal(ta, tb)
 
 
+def test_per_level_launches_equal_batched_bitwise():
+    """One stage launch per level (graph and direct) against the fused launch, on the
+    one-step and the 9-species hierarchies."""
+    for bc in (_small_amr(), _small_detailed_amr()):
+        Ua, Ta, ta = run_blocks(bc, 4)
+        Ub, Tb, tb = run_blocks(bc, 4, flags=janc.PLAN_PER_LEVEL)
+        Uc, Tc, tc = run_blocks(bc, 4, flags=janc.PLAN_PER_LEVEL | janc.PLAN_NO_GRAPH)
+        assert np.array_equal(Ua, Ub) and np.array_equal(Ta, Tb) and np.array_equal(ta, tb)
+        assert np.array_equal(Ua, Uc) and np.array_equal(Ta, Tc) and np.array_equal(ta, tc)
+
+
+def test_autotune_chooses_a_candidate_and_keeps_results():
+    """janc_plan_autotune times the six (tile width, workgroup order) candidates on the
+    state and keeps the fastest; stepping with the tuned plan (and with JANC_PLAN_AUTOTUNE,
+    and with the linear order set by hand) gives the default plan's result bitwise."""
+    import torch
+    from gpu_util import init_blocks, context_for
+    bc = _small_detailed_amr()
+    Ua, Ta, ta = run_blocks(bc, 3)
+    ctx = context_for(bc)
+    plan = ctx.plan(janc.domains_of(bc), bc.blocks, bc.pool_cells)
+    U, T = init_blocks(ctx, bc)
+    U_before, T_before = U.clone(), T.clone()
+    print("[gpu] janc_plan_autotune amr 9 species", flush=True)
+    choice, ms = plan.autotune(janc.time_of(bc), U, T, reps=3)
+    print(f"  choice {choice}, ms {ms}", flush=True)
+    assert choice in janc.AUTOTUNE_CANDIDATES
+    assert sorted(ms) == sorted(janc.AUTOTUNE_CANDIDATES) and min(ms.values()) == ms[choice]
+    assert torch.equal(U, U_before) and torch.equal(T, T_before)   # the state is only read
+    t = torch.zeros(1, dtype=torch.float64, device=U.device)
+    ctx.step_blocks(plan, janc.time_of(bc), U, T, 3, t)
+    ctx.sync_status()
+    assert np.array_equal(U.cpu().numpy(), Ua) and np.array_equal(T.cpu().numpy(), Ta)
+    plan.close()
+    ctx.close()
+    Ub, Tb, tb = run_blocks(bc, 3, flags=janc.PLAN_AUTOTUNE)
+    assert np.array_equal(Ub, Ua) and np.array_equal(Tb, Ta) and np.array_equal(tb, ta)
+
+
+def test_linear_schedule_agrees_bitwise():
+    bc = _small_amr()
+    Ua, _, ta = run_blocks(bc, 4)
+    ctx = janc.Context(bc.model, bc.mech)
+    import torch
+    from gpu_util import init_blocks
+    plan = ctx.plan(janc.domains_of(bc), bc.blocks, bc.pool_cells)
+    plan.set_schedule(32, 1)
+    U, T = init_blocks(ctx, bc)
+    t = torch.zeros(len(bc.domains), dtype=torch.float64, device=U.device)
+    print("[gpu] janc_step_blocks linear schedule, 32-wide tiles", flush=True)
+    ctx.step_blocks(plan, janc.time_of(bc), U, T, 4, t)
+    ctx.sync_status()
+    assert np.array_equal(U.cpu().numpy(), Ua) and np.array_equal(t.cpu().numpy(), ta)
+    plan.close()
+    ctx.close()
+
+
 @pytest.mark.parametrize("tile", [16, 32, 64])
 def test_tile_shapes_agree(tile):
     bc = _small_amr()
@@ -208,19 +265,67 @@ def test_full_jacobian_strang_crossover_vs_oracle():
 
 
 # ------------------------------------------------------------------ full-size workloads
+def _segments_vs_oracle(bcase, checkpoints, bars=None, crossover=False):
+    """Advance a block table on the GPU (batched tiles, graph replay: the benchmark's
+    launch form) and on the oracle, comparing every valid cell at each checkpoint."""
+    import torch
+    from gpu_util import init_blocks, context_for
+    flags = janc.PLAN_CROSSOVER if crossover else 0
+    ctx = context_for(bcase)
+    plan = ctx.plan(janc.domains_of(bcase), bcase.blocks, bcase.pool_cells, flags)
+    U, T = init_blocks(ctx, bcase)
+    t = torch.zeros(len(bcase.domains), dtype=torch.float64, device=U.device)
+    Uo, To = oracle.block_state(bcase)
+    to = None
+    valid = np.zeros(bcase.pool_cells, bool)
+    for b in bcase.blocks[bcase.blocks["valid"] != 0]:
+        valid[b["offset"]:b["offset"] + b["nx"] * b["ny"]] = True
+    n = 0
+    for N in checkpoints:
+        print(f"[gpu] janc_step_blocks {bcase.name} crossover={crossover} steps {n}..{N}",
+              flush=True)
+        ctx.step_blocks(plan, janc.time_of(bcase), U, T, N - n, t)
+        ctx.sync_status()
+        Uo, To, to, _, _ = oracle.step_blocks(bcase, Uo, To, N - n, t=to, crossover=crossover)
+        n = N
+        e = rel_err(U.cpu().numpy()[:, valid], Uo[:, valid])
+        eT = rel_err(T.cpu().numpy()[None, valid], To[None, valid])[0]
+        bar = TOL if bars is None else np.maximum(TOL, bars[N])
+        print(f"  N={N}: per-field rel err {np.array2string(e, precision=2)}, T {eT:.2e}",
+              flush=True)
+        assert np.all(e <= bar), (N, e, bar)
+        assert eT <= np.max(bar)
+        assert np.allclose(t.cpu().numpy(), to, rtol=1e-12, atol=0)
+    plan.close()
+    ctx.close()
+
+
+@pytest.mark.timeout(900)
 def test_full_amr_workload_vs_oracle():
     """The timed 9-species AMR workload (637 blocks, 1,975,360 cells) in the launch form the
-    benchmark times (batched tiles, graph replay), element by element."""
-    _cmp_blocks(amr_case(), 2)
+    benchmark times (batched tiles, graph replay), element by element, over 20 synchronous
+    steps."""
+    _segments_vs_oracle(amr_case(), [2, 20])
 
 
+@pytest.mark.timeout(900)
 def test_full_amr_workload_crossover_vs_oracle():
-    _cmp_blocks(amr_case(), 1, crossover=True)
+    """The same workload in the crossover advance over 4 level-0 steps (28 level steps)."""
+    _segments_vs_oracle(amr_case(), [1, 4], crossover=True)
 
 
+@pytest.mark.timeout(900)
 def test_full_ensemble_vs_oracle():
-    """All 64 instances (32 1-D, 32 2-D) of the ensemble workload."""
-    _cmp_blocks(ensemble_case(), 5)
+    """All 64 instances (32 1-D, 32 2-D) of the ensemble workload over 100 steps; each field
+    held to max(1e-10, 2 x the oracle's own floor at N) (one-ulp density change or fused
+    multiply-add contraction; tests/golden/ensemble_64_floor.json, written by
+    tests/golden/make_floors.py)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "ensemble_64_floor.json")) as f:
+        floor = {int(k): 2.0 * np.array(v) for k, v in json.load(f)["floor"].items()}
+    _segments_vs_oracle(ensemble_case(), sorted(floor), bars=floor)
 
 
 # ------------------------------------------------------------------ profiling entry point

@@ -71,9 +71,37 @@ def test_detonation_many_steps_small():
     _compare(detonation_tube_case(nx=128, ny=32, seed=22), 400)
 
 
-def test_detonation_tube_1024x128_full_size():
-    """1024 x 128 tube (the benchmark's uniform workload) for 60 steps."""
-    _compare(detonation_tube_case(), 60)
+@pytest.mark.timeout(900)
+def test_detonation_tube_1024x128_to_1000_steps():
+    """The full 1024 x 128 tube over its stated 1000 steps, compared every 100 steps. The
+    front is unstable, so round-off grows with N: each field is held to max(1e-10, 2 x the
+    oracle's own floor at N): the larger change of the oracle's result under a one-ulp
+    density change or under fused multiply-add contraction (tests/golden/
+    tube_1024x128_floor.json, written by tests/golden/make_floors.py)."""
+    import paper_2504_13750_amd as janc
+    from test_oracle_floors import tube_floor_golden
+    floor = tube_floor_golden()
+    c = detonation_tube_case()
+    torch, dev = torch_dev()
+    ctx = context_for(c)
+    phys = janc.physics_of(c)
+    U, T = ctx.init_state(phys, torch.tensor(c.W, dtype=torch.float64, device=dev))
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    Uo, To = oracle.case_state(c)
+    to, n = 0.0, 0
+    for N in sorted(floor):
+        print(f"[gpu] janc_step {c.name} 1024x128 steps {n}..{N}", flush=True)
+        ctx.step(janc.grid_of(c), phys, janc.time_of(c), U, T, N - n, t)
+        ctx.sync_status()
+        Uo, To, to, _, _ = oracle.step(c, Uo, To, N - n, t=to)
+        n = N
+        e = rel_err(U.cpu().numpy(), Uo)
+        bar = np.maximum(TOL, 2.0 * floor[N])
+        print(f"  N={N}: per-field rel err {np.array2string(e, precision=2)}, floor "
+              f"{np.array2string(floor[N], precision=2)}", flush=True)
+        assert np.all(e <= bar), (N, e, bar)
+        assert t.item() == pytest.approx(to, rel=1e-12)
+    ctx.close()
 
 
 @pytest.mark.parametrize("shape", [(3, 3), (5, 1), (3, 1), (17, 9), (256, 1), (700, 1)])
@@ -221,20 +249,15 @@ def test_adiabatic_reactor_reaches_gibbs_equilibrium(start):
     """An 8 x 8 periodic grid in one 0-D state with the complete-channel mechanism (30
     reactions), 200 steps each of 1e-10, 1e-9, 1e-8 and 1e-7 s: the GPU matches the oracle
     and its temperature is the independent Gibbs equilibrium temperature of the mixture.
-    From the fresh mixture the relaxation is ill-conditioned: on the oracle itself a change
-    of 1e-15 (relative) in the initial species densities moves the final species by 1e-9 to
-    4e-9, so there the GPU is held to 1e-8 against the oracle (1e-10 from the atoms, where
-    the same change moves nothing beyond 2e-15), and both starts to the Gibbs state."""
+    Bar per field: max(1e-10, 2 x the oracle's floor), the floor measured here as the
+    oracle's own change under a +-1e-15 relative change of the initial species densities
+    (rounding level from the atoms; above 1e-10 from the fresh mixture, whose relaxation
+    is ill-conditioned)."""
     import refsol
     from cases.mechanism import complete_mechanism
-    from test_oracle_chemistry import _reactor_start
+    from test_oracle_floors import reactor_case, reactor_floor, REACTOR_DTS
     mech = complete_mechanism()
-    T0, Y = _reactor_start(mech, start)
-    W = np.zeros((4 + mech.ns - 1, 8, 8))
-    W[0], W[3] = 20 * 101325.0, T0
-    W[4:] = Y[:-1, None, None]
-    c = Case(name=f"reactor-{start}", model=MODEL_DETAILED, nx=8, ny=8, dx=1e-3, dy=1e-3,
-             bc=[BC_PERIODIC] * 4, W=W, mech=mech)
+    c = reactor_case(mech, start, n=8)
     import paper_2504_13750_amd as janc
     print(f"[gpu] janc_step {c.name} 8x8, 4 x 200 steps", flush=True)
     torch, dev = torch_dev()
@@ -242,7 +265,7 @@ def test_adiabatic_reactor_reaches_gibbs_equilibrium(start):
     phys = janc.physics_of(c)
     U, T = ctx.init_state(phys, torch.tensor(c.W, dtype=torch.float64, device=dev))
     t = torch.zeros(1, dtype=torch.float64, device=dev)
-    for dt in (1e-10, 1e-9, 1e-8, 1e-7):
+    for dt in REACTOR_DTS:
         ctx.step(janc.grid_of(c), phys, janc.time_of(c, dt_fixed=dt), U, T, 200, t)
     ctx.sync_status()
     Ug, Tg = U.cpu().numpy(), T.cpu().numpy()
@@ -251,12 +274,14 @@ def test_adiabatic_reactor_reaches_gibbs_equilibrium(start):
     rho, e = Uo[0, 0, 0], Uo[3, 0, 0] / Uo[0, 0, 0]
     X0 = np.r_[Uo[4:, 0, 0], rho - Uo[4:, 0, 0].sum()] / mech.M
     Teq, Xeq = refsol.equilibrium_T(mech, rho, e, mech.comp.T.astype(float) @ X0)
-    for dt in (1e-10, 1e-9, 1e-8, 1e-7):
+    for dt in REACTOR_DTS:
         Uo, To, _, _, _ = oracle.step(c, Uo, To, 200, dt_fixed=dt)
     err = rel_err(Ug, Uo)
+    bar = np.maximum(TOL, 2.0 * reactor_floor(oracle, start))
     print(f"  reactor {start}: GPU T {Tg[0, 0]:.10f}, Gibbs {Teq:.10f}, per-field rel err "
-          f"{np.array2string(err, precision=2)}", flush=True)
-    assert np.all(err <= (TOL if start == "atoms-600K" else 1e-8))
+          f"{np.array2string(err, precision=2)}, bar {np.array2string(bar, precision=2)}",
+          flush=True)
+    assert np.all(err <= bar)
     assert Tg[0, 0] == pytest.approx(Teq, rel=1e-9)
     X = np.r_[Ug[4:, 0, 0], rho - Ug[4:, 0, 0].sum()] / mech.M
     assert np.max(np.abs(X - Xeq)) <= 1e-7 * X.sum()
