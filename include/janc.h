@@ -153,6 +153,26 @@ janc_status janc_step(janc_ctx *ctx, const janc_grid *grid, const janc_physics *
                       const janc_time *time, double *U, double *T, int nsteps, double *t,
                       double *dt_log, void *stream);
 
+/* Bytes of the static device array that holds every workspace of janc_step_noalloc
+ * (one per device, resident from the library's first janc_create on that device until
+ * the process ends). */
+#define JANC_NOALLOC_SCRATCH_BYTES (64ll << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture, serving
+ * loops, harnesses that forbid hipMalloc): janc_step with the same arguments, results
+ * and errors, that calls no hipMalloc, hipFree or allocating library routine. Its stage
+ * states, reductions and plan tables live in the static array above: a grid needs about
+ * 16 (nfields + 1) bytes per cell plus small tables (9 species: about 320 k cells; the
+ * one-step model: about 690 k cells); larger grids are rejected with JANC_EINVAL and a
+ * message, before any device work. The steps are launched directly (no graph); the tables
+ * are copied into the array on `stream` at every call. Every call on a device shares that
+ * device's array, which keeps the last call's contents: calls that overlap on one device
+ * (other streams, other threads, other contexts) race and must be serialized by the
+ * caller. */
+janc_status janc_step_noalloc(janc_ctx *ctx, const janc_grid *grid, const janc_physics *phys,
+                              const janc_time *time, double *U, double *T, int nsteps,
+                              double *t, double *dt_log, void *stream);
+
 /* ------------------------------------------------------------------ block tables */
 /* A domain is one independent problem: a level-0 grid, its boundaries, its
  * physics and the number of refinement levels (ratio 2, Sec. 3.1). Each domain

@@ -256,6 +256,19 @@ class Context:
                                       _dptr(dt_log, None, "dt_log"),
                                       C.c_void_p(_stream_handle(stream))))
 
+    def step_noalloc(self, grid, phys, time, U, T, nsteps, t, dt_log=None, stream=None):
+        """Context.step through janc_step_noalloc: no device allocation; every workspace
+        lives in the library's static scratch array (JANC_NOALLOC_SCRATCH_BYTES per device),
+        shared by every call on the device."""
+        n = grid.nx * grid.ny
+        if dt_log is not None and dt_log.numel() < int(nsteps):
+            raise ValueError(f"dt_log has {dt_log.numel()} elements, the call writes {int(nsteps)}")
+        self._check(L.lib().janc_step_noalloc(self.h, C.byref(grid), C.byref(phys), C.byref(time),
+                                              _dptr(U, self.nfields * n, "U"), _dptr(T, n, "T"),
+                                              int(nsteps), _dptr(t, 1, "t"),
+                                              _dptr(dt_log, None, "dt_log"),
+                                              C.c_void_p(_stream_handle(stream))))
+
     def plan(self, domains, blocks, pool_cells, flags=PLAN_DEFAULT):
         blocks = np.ascontiguousarray(blocks, dtype=BLOCK_DTYPE)
         h = C.c_void_p()

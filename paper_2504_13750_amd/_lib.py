@@ -60,6 +60,8 @@ EXPORTS = {
     "janc_init_state": (I, [VP, C.POINTER(janc_physics), C.c_longlong, VP, VP, VP, VP]),
     "janc_step": (I, [VP, C.POINTER(janc_grid), C.POINTER(janc_physics), C.POINTER(janc_time),
                       VP, VP, I, VP, VP, VP]),
+    "janc_step_noalloc": (I, [VP, C.POINTER(janc_grid), C.POINTER(janc_physics),
+                              C.POINTER(janc_time), VP, VP, I, VP, VP, VP]),
     "janc_plan_create": (I, [VP, I, C.POINTER(janc_domain), I, VP, C.c_longlong, I,
                              C.POINTER(VP)]),
     "janc_plan_destroy": (None, [VP]),

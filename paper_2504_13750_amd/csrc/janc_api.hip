@@ -10,12 +10,18 @@
 #include <string>
 #include <array>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/janc.h"
 #include "janc_internal.h"
 
 using namespace janc;
+
+// The workspace of janc_step_noalloc: one array per device, held until the process ends.
+// Host code never uses the array's name as an address: its device address comes from
+// hipGetSymbolAddress, once per device, with that device current (noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[JANC_NOALLOC_SCRATCH_BYTES];
 
 static_assert(MAXP == JANC_MAX_PROBES, "probe limit of the adjoint kernels");
 static_assert(MAXF == JANC_MAX_FIELDS && MAXL == JANC_MAX_LEVELS, "table limits");
@@ -35,6 +41,11 @@ struct janc_ctx {
     janc_plan* uplan = nullptr;
     janc_grid ugrid{};
     janc_physics uphys{};
+    // cached plan of janc_step_noalloc: host tables, device addresses inside the
+    // static scratch array
+    janc_plan* nplan = nullptr;
+    janc_grid ngrid{};
+    janc_physics nphys{};
     // adjoint workspace (grown on demand)
     double* adj_mem = nullptr;
     size_t adj_doubles = 0;
@@ -86,7 +97,7 @@ struct janc_plan {
     double* ddt = nullptr;
     int* dstep = nullptr;
     int* dfine = nullptr;          // concatenated fine lists
-    std::vector<int> fine_off;
+    std::vector<int> fine_off, fine_flat;
     int* dring = nullptr;
     double *U1 = nullptr, *U2 = nullptr, *T1 = nullptr, *T2 = nullptr;
     // graph cache
@@ -95,6 +106,17 @@ struct janc_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipEvent_t gdone = nullptr;    // recorded after the last replay of the graph
+    // Workspace source. arena == nullptr: every device array is a hipMalloc of its own.
+    // Otherwise arrays are carved from [arena, arena + arena_cap) (the static scratch
+    // array of janc_step_noalloc) and nothing is copied at build time: the host tables
+    // are uploaded and the Dirichlet rows converted by stage_tables() before each use.
+    char* arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+    struct Upload { void* dst; const void* src; size_t bytes; };
+    std::vector<Upload> uploads;
+    struct DirRow { int row; double gamma, R, Q; double prim[MAXF]; };
+    std::vector<DirRow> dir_rows;
+    double* dir_w = nullptr;       // arena: primitive staging of the Dirichlet rows
 };
 
 namespace {
@@ -156,11 +178,39 @@ void plan_free(janc_plan* p) {
     if (p->gexec) hipGraphExecDestroy(p->gexec);
     if (p->graph) hipGraphDestroy(p->graph);
     if (p->gdone) hipEventDestroy(p->gdone);
-    void* ptrs[] = {p->ddom, p->dblk, p->dmap, p->dtiles, p->ddir, p->dred, p->ddt, p->dstep,
-                    p->dfine, p->dring, p->U1, p->U2, p->T1, p->T2};
-    for (void* q : ptrs)
-        if (q) hipFree(q);
+    if (!p->arena) {
+        void* ptrs[] = {p->ddom, p->dblk, p->dmap, p->dtiles, p->ddir, p->dred, p->ddt, p->dstep,
+                        p->dfine, p->dring, p->U1, p->U2, p->T1, p->T2};
+        for (void* q : ptrs)
+            if (q) hipFree(q);
+    }
     delete p;
+}
+
+// Device array of a plan: its own hipMalloc, or the next 256-byte aligned piece of the
+// plan's arena (nothing is allocated; too little room is an argument error).
+template <class T> janc_status palloc(janc_plan* P, T** p, size_t n) {
+    if (!P->arena) return dalloc(P->ctx, p, n);
+    *p = nullptr;
+    if (n == 0) n = 1;
+    const size_t off = (P->arena_used + 255) & ~(size_t)255;
+    const size_t bytes = n * sizeof(T);
+    if (off > P->arena_cap || bytes > P->arena_cap - off)
+        return fail(P->ctx, JANC_EINVAL,
+                    "the grid needs more than the %zu bytes of the static scratch of janc_step_noalloc",
+                    P->arena_cap);
+    *p = (T*)(P->arena + off);
+    P->arena_used = off + bytes;
+    return JANC_OK;
+}
+
+// A host table on the device: copied now, or (arena) recorded for stage_tables().
+template <class T> janc_status pupload(janc_plan* P, T** p, const std::vector<T>& v) {
+    if (!P->arena) return upload(P->ctx, p, v);
+    janc_status st = palloc(P, p, v.size());
+    if (st) return st;
+    if (!v.empty()) P->uploads.push_back({(void*)*p, (const void*)v.data(), v.size() * sizeof(T)});
+    return JANC_OK;
 }
 
 // --------------------------------------------------------------- mechanism
@@ -229,12 +279,15 @@ struct LevelMap {
 };
 
 janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, const janc_block* blocks,
-                       long long pool, int flags, janc_plan** out) {
+                       long long pool, int flags, janc_plan** out, char* arena = nullptr,
+                       size_t arena_cap = 0) {
     *out = nullptr;
     if (nd < 1 || nb < 1 || pool < 1 || !doms || !blocks)
         return fail(c, JANC_EINVAL, "empty block table");
     std::unique_ptr<janc_plan, void (*)(janc_plan*)> P(new janc_plan(), plan_free);
     P->ctx = c;
+    P->arena = arena;
+    P->arena_cap = arena_cap;
     if (flags & ~(JANC_PLAN_PER_BLOCK | JANC_PLAN_NO_GRAPH | JANC_PLAN_CROSSOVER | JANC_PLAN_PER_LEVEL |
                   JANC_PLAN_AUTOTUNE))
         return fail(c, JANC_EINVAL, "unknown plan flags");
@@ -412,8 +465,22 @@ janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, con
     // ---- Dirichlet rows (conserved state + T), converted on the device
     P->hdir.assign((size_t)std::max(ndir, 1) * (MAXF + 1), 0.0);
     janc_status st;
-    if ((st = dalloc(c, &P->ddir, P->hdir.size()))) return st;
-    {
+    if ((st = palloc(P.get(), &P->ddir, P->hdir.size()))) return st;
+    if (P->arena) {
+        for (int d = 0; d < nd; ++d)
+            for (int s = 0; s < 4; ++s) {
+                const int row = P->hdom[d].dir[s];
+                if (row < 0) continue;
+                janc_plan::DirRow r{};
+                r.row = row;
+                r.gamma = doms[d].phys.gamma;
+                r.R = doms[d].phys.R;
+                r.Q = doms[d].phys.Q;
+                for (int f = 0; f < nU; ++f) r.prim[f] = doms[d].grid.bc_prim[s][f];
+                P->dir_rows.push_back(r);
+            }
+        if ((st = palloc(P.get(), &P->dir_w, (size_t)std::max(ndir, 1) * MAXF))) return st;
+    } else {
         double* dW = nullptr;
         if ((st = dalloc(c, &dW, MAXF))) return st;
         for (int d = 0; d < nd; ++d)
@@ -437,25 +504,24 @@ janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, con
     P->nblk = (int)P->hblk.size();
     for (const auto& h : P->hblk) P->cells += (long long)h.nx * h.ny;
     // ---- device tables and workspaces
-    if ((st = upload(c, &P->ddom, P->hdom))) return st;
-    if ((st = upload(c, &P->dblk, P->hblk))) return st;
-    if ((st = upload(c, &P->dmap, P->hmap))) return st;
-    std::vector<int> fl;
+    if ((st = pupload(P.get(), &P->ddom, P->hdom))) return st;
+    if ((st = pupload(P.get(), &P->dblk, P->hblk))) return st;
+    if ((st = pupload(P.get(), &P->dmap, P->hmap))) return st;
     for (int l = 0; l <= P->maxlev; ++l) {
-        P->fine_off.push_back((int)fl.size());
-        fl.insert(fl.end(), P->fine[l].begin(), P->fine[l].end());
+        P->fine_off.push_back((int)P->fine_flat.size());
+        P->fine_flat.insert(P->fine_flat.end(), P->fine[l].begin(), P->fine[l].end());
     }
-    if ((st = upload(c, &P->dfine, fl))) return st;
-    if ((st = upload(c, &P->dring, P->ring_blocks))) return st;
+    if ((st = pupload(P.get(), &P->dfine, P->fine_flat))) return st;
+    if ((st = pupload(P.get(), &P->dring, P->ring_blocks))) return st;
     P->red_stride = 2 * P->nunits + nd;
     const int ntrip = (flags & JANC_PLAN_CROSSOVER) ? P->maxlev + 1 : 1;   // slot sets
-    if ((st = dalloc(c, &P->dred, (size_t)RED_BUFS * ntrip * P->red_stride))) return st;
-    if ((st = dalloc(c, &P->ddt, nd))) return st;
-    if ((st = dalloc(c, &P->dstep, 1))) return st;
-    if ((st = dalloc(c, &P->U1, (size_t)nU * pool))) return st;
-    if ((st = dalloc(c, &P->U2, (size_t)nU * pool))) return st;
-    if ((st = dalloc(c, &P->T1, (size_t)pool))) return st;
-    if ((st = dalloc(c, &P->T2, (size_t)pool))) return st;
+    if ((st = palloc(P.get(), &P->dred, (size_t)RED_BUFS * ntrip * P->red_stride))) return st;
+    if ((st = palloc(P.get(), &P->ddt, nd))) return st;
+    if ((st = palloc(P.get(), &P->dstep, 1))) return st;
+    if ((st = palloc(P.get(), &P->U1, (size_t)nU * pool))) return st;
+    if ((st = palloc(P.get(), &P->U2, (size_t)nU * pool))) return st;
+    if ((st = palloc(P.get(), &P->T1, (size_t)pool))) return st;
+    if ((st = palloc(P.get(), &P->T2, (size_t)pool))) return st;
     *out = P.release();
     return JANC_OK;
 }
@@ -488,9 +554,9 @@ janc_status build_tiles(janc_ctx* c, janc_plan* P) {
         }
         P->lev_count[l] = (int)P->htiles.size() - P->lev_first[l];
     }
-    if (P->dtiles) hipFree(P->dtiles);
+    if (P->dtiles && !P->arena) hipFree(P->dtiles);
     P->dtiles = nullptr;
-    return upload(c, &P->dtiles, P->htiles);
+    return pupload(P, &P->dtiles, P->htiles);
 }
 
 StageArgs base_args(janc_plan* P, const janc_time* tm, double* U, double* T, double* t,
@@ -868,6 +934,90 @@ janc_status uniform_plan(janc_ctx* c, const janc_grid* g, const janc_physics* ph
     c->ugrid = *g;
     c->uphys = *ph;
     return JANC_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free stepping
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[NOALLOC_MAX_DEVICES] = {};
+
+// Resolves (once) and returns the device address of this device's scratch array;
+// the device must be current.
+janc_status noalloc_scratch(janc_ctx* c, char** out) {
+    *out = nullptr;
+    if (c->device < 0 || c->device >= NOALLOC_MAX_DEVICES)
+        return fail(c, JANC_EINVAL, "device %d beyond the %d devices of the static scratch", c->device,
+                    NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[c->device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hipfail(c, e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(c, JANC_EHIP, "hipGetSymbolAddress(scratch) returned no address");
+        g_scratch[c->device] = (char*)p;
+    }
+    *out = g_scratch[c->device];
+    return JANC_OK;
+}
+
+// Stream-ordered set-up of an arena plan before its launches: the host tables are
+// copied into the scratch array and the Dirichlet rows converted there.
+janc_status stage_tables(janc_ctx* c, janc_plan* P, hipStream_t s) {
+    for (const auto& u : P->uploads)
+        HIPCHK(c, hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, s), "table copy");
+    if (!P->dir_rows.empty()) {
+        static_assert(sizeof(janc_plan::DirRow::prim) == MAXF * sizeof(double), "row layout");
+        for (size_t r = 0; r < P->dir_rows.size(); ++r)
+            HIPCHK(c, hipMemcpyAsync(P->dir_w + r * MAXF, P->dir_rows[r].prim, MAXF * sizeof(double),
+                                     hipMemcpyHostToDevice, s), "Dirichlet copy");
+        for (size_t r = 0; r < P->dir_rows.size(); ++r) {
+            const janc_plan::DirRow& d = P->dir_rows[r];
+            double* row = P->ddir + (size_t)d.row * (MAXF + 1);
+            HIPCHK(c, launch_prim_to_cons(c->model, c->ns, c->dmech, d.gamma, d.R, d.Q, 1,
+                                          P->dir_w + r * MAXF, row, row + MAXF, 1, 1, s),
+                   "Dirichlet state");
+        }
+    }
+    return JANC_OK;
+}
+
+// janc_step with every workspace in the static scratch array: the uniform plan's host
+// tables are built (and cached) on the host, their device arrays are pieces of the
+// scratch array, and the steps are launched directly (no graph).
+janc_status run_step_noalloc(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
+                             const janc_time* tm, double* U, double* T, int nsteps, double* t,
+                             double* dt_log, hipStream_t s) {
+    HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    char* base = nullptr;
+    janc_status st = noalloc_scratch(c, &base);
+    if (st) return st;
+    if (!(c->nplan && std::memcmp(&c->ngrid, g, sizeof(*g)) == 0 &&
+          std::memcmp(&c->nphys, ph, sizeof(*ph)) == 0)) {
+        plan_free(c->nplan);
+        c->nplan = nullptr;
+        janc_domain D;
+        D.grid = *g;
+        D.phys = *ph;
+        D.nlevels = 1;
+        janc_block B{0, 0, 0, 0, g->nx, g->ny, 0, 1, 0};
+        janc_plan* P = nullptr;
+        st = build_plan(c, 1, &D, 1, &B, (long long)g->nx * g->ny, JANC_PLAN_NO_GRAPH, &P, base,
+                        (size_t)JANC_NOALLOC_SCRATCH_BYTES);
+        if (st) return st;
+        if (g->ny > 1 && g->nx >= 64 && g->ny < 16) P->tile_w = 64;
+        else if (g->ny > 1 && g->nx >= 32 && g->ny < 32) P->tile_w = 32;
+        st = build_tiles(c, P);
+        if (st) {
+            plan_free(P);
+            return st;
+        }
+        c->nplan = P;
+        c->ngrid = *g;
+        c->nphys = *ph;
+    }
+    st = stage_tables(c, c->nplan, s);
+    if (st) return st;
+    return run_steps(c, c->nplan, tm, U, T, nsteps, t, dt_log, s);
 }
 
 // ---------------------------------------------------------------- discrete adjoint
@@ -1319,6 +1469,10 @@ janc_status janc_create(janc_ctx** out, int model, const janc_mech* mech, int de
         c->ns = mech->ns;
     }
     c->nU = n_fields(model, c->ns);
+    {
+        char* scr = nullptr;   // the allocation-free entry point's array on this device
+        if (noalloc_scratch(c.get(), &scr)) return JANC_EHIP;
+    }
     if (dalloc(c.get(), &c->dstatus, 1)) return JANC_ENOMEM;
     if (hipMemset(c->dstatus, 0, sizeof(unsigned)) != hipSuccess) return JANC_EHIP;
     *out = c.release();
@@ -1329,6 +1483,7 @@ void janc_destroy(janc_ctx* c) {
     if (!c) return;
     hipSetDevice(c->device);
     plan_free(c->uplan);
+    plan_free(c->nplan);
     if (c->dmech) hipFree(c->dmech);
     if (c->dstatus) hipFree(c->dstatus);
     if (c->adj_mem) hipFree(c->adj_mem);
@@ -1416,6 +1571,7 @@ janc_status janc_plan_autotune(janc_ctx* c, janc_plan* P, const janc_time* tm, c
                                const double* T, int reps, int* choice, double* ms, void* stream) {
     if (!c || !P || !tm || !U || !T || reps < 1 || reps > 1000) return fail(c, JANC_EINVAL, "bad arguments");
     if (P->ctx != c) return fail(c, JANC_EINVAL, "plan belongs to another context");
+    if (P->arena) return fail(c, JANC_EINVAL, "plan of the allocation-free entry point");
     if (janc_status st = check_time(c, tm)) return st;
     janc_status st = autotune(c, P, tm, (double*)U, (double*)T, reps, ms, (hipStream_t)stream);
     if (st) return st;
@@ -1449,6 +1605,14 @@ janc_status janc_step(janc_ctx* c, const janc_grid* g, const janc_physics* ph, c
     janc_status st = uniform_plan(c, g, ph);
     if (st) return st;
     return run_steps(c, c->uplan, tm, U, T, nsteps, t, dt_log, (hipStream_t)stream);
+}
+
+janc_status janc_step_noalloc(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
+                              const janc_time* tm, double* U, double* T, int nsteps, double* t,
+                              double* dt_log, void* stream) {
+    if (!c || !g || !ph || !tm || !U || !T || !t || nsteps < 0) return fail(c, JANC_EINVAL, "bad arguments");
+    if (janc_status st = check_time(c, tm)) return st;
+    return run_step_noalloc(c, g, ph, tm, U, T, nsteps, t, dt_log, (hipStream_t)stream);
 }
 
 janc_status janc_profile_step(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U,
