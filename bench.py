@@ -64,8 +64,8 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-STAGE_SOURCES = ("csrc/janc_device.h", "csrc/janc_internal.h", "csrc/janc_kernels.hip",
-                 "build.py")
+STAGE_SOURCES = ("csrc/janc_device.h", "csrc/janc_internal.h", "csrc/janc_kernels.h",
+                 "csrc/janc_species.hip", "build.py")
 
 
 def kernel_source_hash():
@@ -485,6 +485,55 @@ def main():
         log(f"[bench] adjoint {ta * 1e3:.2f} ms vs forward {tf * 1e3:.2f} ms: "
             f"{ta / tf:.2f}x")
         actx.close()
+
+        # the detailed model (9 species: NASA-7 Newton, point-implicit chemistry)
+        from cases.amr import detailed_adjoint_case
+        d = detailed_adjoint_case(nx=128, ny=64, nsteps=40)
+        dc = d["case"]
+        dctx = janc.Context(janc.DETAILED, dc.mech)
+        dph, dg = janc.physics_of(dc), janc.grid_of(dc)
+        dW0 = torch.tensor(dc.W, dtype=torch.float64, device=dev)
+        # the fixed dt: the CFL step (at cfl_dt) of the initial state, from one GPU step
+        U1, T1 = dctx.init_state(dph, dW0)
+        dtl = torch.zeros(1, dtype=torch.float64, device=dev)
+        dctx.step(dg, dph, janc.make_time(cfl=d["cfl_dt"]), U1, T1, 1,
+                  torch.zeros(1, dtype=torch.float64, device=dev), dtl)
+        dc.dt_fixed = float(dtl.item())
+        del U1, T1
+        dtm = janc.make_time(0.0, dc.dt_fixed, 0.0)
+        dk = 10
+
+        def dfwd():
+            U0, T0 = dctx.init_state(dph, dW0)
+            t0 = torch.zeros(1, dtype=torch.float64, device=dev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            dctx.step(dg, dph, dtm, U0, T0, dc.nsteps, t0)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / 1e3
+
+        def dadj():
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            dctx.adjoint(dg, dph, dtm, dW0, dc.nsteps, dk, d["probe_cell"], d["probe_w"])
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / 1e3
+
+        dfwd()
+        dadj()
+        tfd = min(dfwd() for _ in range(3))
+        tad = min(dadj() for _ in range(3))
+        dctx.sync_status()
+        dctx.close()
+        adjoint["detailed"] = {"workload": f"9-species front {dc.nx}x{dc.ny}, {dc.nsteps} steps, "
+                                           f"checkpoints every {dk}",
+                               "forward_s": tfd, "adjoint_s": tad, "adjoint_over_forward": tad / tfd}
+        log(f"[bench] detailed-model adjoint {tad * 1e3:.2f} ms vs forward {tfd * 1e3:.2f} ms: "
+            f"{tad / tfd:.2f}x")
         return adjoint
     adjoint = None if args.no_adjoint else optional("adjoint", _adjoint)
 

@@ -148,3 +148,28 @@ def detailed_front_case(nx: int = 128, ny: int = 64, dx: float = 25e-6, mech: Me
     return Case(name=f"front{nx}x{ny}", model=MODEL_DETAILED, nx=nx, ny=ny, dx=dx, dy=dx,
                 bc=[BC_ZEROGRAD, BC_ZEROGRAD, BC_SLIPWALL, BC_SLIPWALL], W=W, mech=mech,
                 cfl=cfl, nsteps=nsteps)
+
+
+def detailed_adjoint_case(nx: int = 32, ny: int = 16, dx: float = 25e-6, nsteps: int = 8,
+                          seed: int = 2504, cfl_dt: float = 0.4, mech: Mechanism = None) -> dict:
+    """Adjoint workload of the detailed model: the 9-species front state with a seeded
+    velocity field (u shifted by 40 m/s, v = 25 + 15 sin(2 pi x / L_x) m/s) and +-0.5 %
+    noise on p and T, so that no speed is zero and no two cells tie for the largest wave
+    speed (|v| and the max are then differentiable at the state). Fixed dt = cfl_dt over
+    the CFL bound of the initial state; zero-gradient W/E, slip walls S/N; probes at two
+    wall cells and two interior cells."""
+    if mech is None:
+        mech = synthetic_mechanism()
+    c = detailed_front_case(nx=nx, ny=ny, dx=dx, mech=mech, nsteps=nsteps)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W = c.W.copy()
+    xc = (np.arange(nx) + 0.5) / nx
+    W[1] = W[1] + 40.0
+    W[2] = 25.0 + 15.0 * np.sin(2.0 * math.pi * xc)[None, :] * np.ones((ny, 1))
+    W[0] = W[0] * (1.0 + 0.005 * rng.uniform(-1.0, 1.0, size=W[0].shape))
+    W[3] = W[3] * (1.0 + 0.005 * rng.uniform(-1.0, 1.0, size=W[3].shape))
+    c.W = W
+    probes = [(nx // 4, 0), (3 * nx // 4, ny - 1), (nx // 2, ny // 2), (nx // 8, ny // 3)]
+    probe_cell = np.array([j * nx + i for (i, j) in probes], dtype=np.int32)
+    probe_w = np.array([1.0, 0.5, 2.0, 1.0])
+    return {"case": c, "probe_cell": probe_cell, "probe_w": probe_w, "cfl_dt": cfl_dt}

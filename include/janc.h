@@ -64,8 +64,8 @@ enum { JANC_MAX_FIELDS = 16, JANC_MAX_LEVELS = 8, JANC_MAX_PROBES = 8 };
  * [nr][ns] integer stoichiometry (Eq. 4.6), at most 3 molecules per side;
  * tb [nr][ns] third-body efficiencies, used when has_tb[i] (Eq. 4.7);
  * reversible [nr]: k_b = k_f / K_eq (Eq. 4.9) when set, else 0. The last
- * species is the complement 1 - sum(Y). Kernels are compiled for ns = 2 and
- * ns = 9 (other sizes: JANC_EINVAL); nr <= 64. */
+ * species is the complement 1 - sum(Y). Kernels are compiled for every ns from 2 to
+ * 12 (other sizes: JANC_EINVAL); nr <= 64. */
 typedef struct {
     int ns, nr;
     const double *M, *nasa, *A, *b, *Ea;
@@ -314,16 +314,20 @@ janc_status janc_profile_step(janc_ctx *ctx, janc_plan *plan, const janc_time *t
 
 /* ------------------------------------------------------------------ adjoint */
 /* Discrete adjoint (the exact gradient of the discrete map) of nsteps steps of
- * janc_step for the one-step model with a fixed dt (time->dt_fixed > 0), in the
- * sense of the adjoint method of Sec. 6.1 (Eq. 6.1-6.5) applied to the discrete
- * trajectory. Loss = sum_{n=1..N} dt * sum_q w_q * p(U^n at cell probe_cell[q]).
- * W0 (device) [5][ny][nx] are initial primitives [rho, u, v, p, Y]; the state is
- * checkpointed every ckpt_every steps and recomputed inside each segment.
- * Outputs (device): loss[1], dL_dW0 [5][ny][nx], dL_dtheta[2] = {dL/dQ, dL/dEa}
- * (Q enters through the equation of state and the initial energy). probe_cell
- * and probe_w are host arrays of nprobes (0 .. JANC_MAX_PROBES) entries; a probe
- * cell out of range, a count out of range, dt_fixed <= 0, t_end > 0 or a model
- * other than the one-step model return JANC_EINVAL. */
+ * janc_step with a fixed dt (time->dt_fixed > 0), in the sense of the adjoint method
+ * of Sec. 6.1 (Eq. 6.1-6.5) applied to the discrete trajectory, for the one-step model
+ * and for the detailed model (Lie splitting and the frozen-T Jacobian: the temperature
+ * Newton of Eq. 4.2-4.5 is differentiated by the implicit-function theorem, the
+ * point-implicit step of Eq. 4.12-4.13 through its transposed solve and the rate
+ * derivatives along its increment). Loss = sum_{n=1..N} dt * sum_q w_q *
+ * p(U^n at cell probe_cell[q]). W0 (device) [nfields][ny][nx] are the initial
+ * primitives in janc_init_state's layout; the state is checkpointed every ckpt_every
+ * steps and recomputed inside each segment. Outputs (device): loss[1], dL_dW0
+ * [nfields][ny][nx], dL_dtheta[2] = {dL/dQ, dL/dEa} of the one-step model (Q enters
+ * through the equation of state and the initial energy), zeros for the detailed model.
+ * probe_cell and probe_w are host arrays of nprobes (0 .. JANC_MAX_PROBES) entries; a
+ * probe cell out of range, a count out of range, dt_fixed <= 0, t_end > 0, the CPG
+ * model, Strang splitting or the species + T Jacobian return JANC_EINVAL. */
 janc_status janc_adjoint(janc_ctx *ctx, const janc_grid *grid, const janc_physics *phys,
                          const janc_time *time, const double *W0, int nsteps, int ckpt_every,
                          int nprobes, const int *probe_cell, const double *probe_w,

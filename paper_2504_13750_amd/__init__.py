@@ -329,7 +329,9 @@ class Context:
 
     def adjoint(self, grid, phys, time, W0, nsteps, ckpt_every, probe_cell, probe_w,
                 stream=None):
-        """Returns (loss, dL/dW0, dL/dtheta) as device tensors ([1], [5, ny, nx], [2])."""
+        """Returns (loss, dL/dW0, dL/dtheta) as device tensors ([1], [nfields, ny, nx], [2]).
+        W0 holds the model's primitives (init_state's layout); dL/dtheta = (dL/dQ, dL/dEa)
+        for the one-step model, zeros for the detailed model."""
         torch = _torch()
         pc = np.ascontiguousarray(probe_cell, dtype=np.int32)
         pw = np.ascontiguousarray(probe_w, dtype=np.float64)
@@ -337,7 +339,7 @@ class Context:
         gW = torch.zeros_like(W0)
         gth = torch.zeros(2, dtype=torch.float64, device=W0.device)
         self._check(L.lib().janc_adjoint(self.h, C.byref(grid), C.byref(phys), C.byref(time),
-                                         _dptr(W0, 5 * grid.nx * grid.ny, "W0"), int(nsteps),
+                                         _dptr(W0, self.nfields * grid.nx * grid.ny, "W0"), int(nsteps),
                                          int(ckpt_every), len(pc), pc.ctypes.data_as(L.PI),
                                          pw.ctypes.data_as(L.PD), _dptr(loss), _dptr(gW),
                                          _dptr(gth), C.c_void_p(_stream_handle(stream))))

@@ -18,6 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjanc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["janc_kernels.hip", "janc_adjoint.hip", "janc_regrid.hip", "janc_api.hip"]
+# the detailed model's kernels: janc_species.hip once per species count (2 .. 12)
+SPECIES = list(range(2, 13))
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-value", "-Wno-unused-result"]
@@ -30,7 +32,14 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
         cmds.append([HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    with cf.ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+    for ns in SPECIES:
+        obj = os.path.join(CSRC, f"janc_species_{ns}.o")
+        cmds.append([HIPCC] + FLAGS + [f"-DJANC_NS={ns}", "-c", os.path.join(CSRC, "janc_species.hip"),
+                                       "-o", obj])
+        objs.append(obj)
+    # the largest translation units first, at most one compiler per host core
+    cmds.sort(key=lambda c: "janc_species" not in c[-3])
+    with cf.ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 4)) as ex:
         for cmd in cmds:
             if verbose:
                 print(" ".join(cmd), flush=True)

@@ -218,7 +218,7 @@ janc_status build_mech(janc_ctx* c, const janc_mech* m) {
     if (!m || m->ns < 2 || m->ns > MAXS || m->nr < 0 || m->nr > MAXR)
         return fail(c, JANC_EINVAL, "mechanism sizes out of range (ns 2..%d, nr 0..%d)", MAXS, MAXR);
     if (!model_supported(DETAILED, m->ns))
-        return fail(c, JANC_EINVAL, "no kernels compiled for ns = %d (available: 2, 9)", m->ns);
+        return fail(c, JANC_EINVAL, "no kernels compiled for ns = %d (available: %d .. %d)", m->ns, JANC_NS_FIRST, JANC_NS_LAST);
     DevMech& d = c->hmech;
     std::memset(&d, 0, sizeof(d));
     d.ns = m->ns;
@@ -1022,15 +1022,23 @@ janc_status run_step_noalloc(janc_ctx* c, const janc_grid* g, const janc_physics
 
 // ---------------------------------------------------------------- discrete adjoint
 // Forward with checkpoints every k steps (and the probe loss), then segments in
-// reverse: recompute the segment from its checkpoint storing every stage input,
-// and sweep its steps backwards through the three stage adjoints.
+// reverse: recompute the segment from its checkpoint storing every stage input (and,
+// for the detailed model, each step's chemistry input with the temperatures of every
+// stored state), and sweep its steps backwards: the chemistry step, then the three
+// stage adjoints.
 janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
                         const janc_time* tm, const double* W0, int N, int K, int np,
                         const int* pc, const double* pw, double* loss, double* gW,
                         double* theta, hipStream_t s) {
-    if (c->model != ONESTEP) return fail(c, JANC_EINVAL, "the adjoint covers the one-step model");
+    const int model = c->model, ns = c->ns, NU = c->nU;
+    const bool det = model == DETAILED;
+    if (model != ONESTEP && !det) return fail(c, JANC_EINVAL, "the adjoint covers the one-step and the detailed models");
     if (!(tm->dt_fixed > 0.0)) return fail(c, JANC_EINVAL, "the adjoint needs a fixed dt (dt_fixed > 0)");
     if (tm->t_end > 0.0) return fail(c, JANC_EINVAL, "the adjoint does not clip to t_end");
+    if (det && tm->split != JANC_SPLIT_LIE)
+        return fail(c, JANC_EINVAL, "the adjoint of the detailed model follows the Lie-split step");
+    if (det && tm->jac != JANC_JAC_FROZEN_T)
+        return fail(c, JANC_EINVAL, "the adjoint of the detailed model uses the frozen-T Jacobian");
     if (g->nx < 3 || (g->ny != 1 && g->ny < 3))
         return fail(c, JANC_EINVAL, "adjoint grid needs nx >= 3 and ny = 1 or ny >= 3");
     const long long n = (long long)g->nx * g->ny;
@@ -1063,26 +1071,28 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     const int nbd = (int)((n + 127) / 128);          // blocks of the cell kernel (128 cells each)
     const long long nix = (long long)(g->nx + 1) * g->ny;
     const long long niy = ag.twod ? (long long)g->nx * (g->ny + 1) : 0;
-    const long long n5 = 5 * n;
+    const long long nf = (long long)NU * n;          // conserved fields of a state
+    const long long sn = det ? nf + n : nf;          // a stored state (+ temperatures)
     const int nsl = 3 * K;                            // stage inputs of one segment
     // workspace layout (doubles)
     struct Seg { size_t off, len; };
     size_t tot = 0;
     auto take = [&](size_t len) { Seg r{tot, len}; tot += (len + 31) & ~(size_t)31; return r; };
-    // segment storage (stage inputs, alpha and argmax) twice: the recompute of
-    // segment sg - 1 on the auxiliary stream overlaps the reverse sweep of sg
-    Seg sS0[2], sS1[2], sS2[2], sApart[2], sAlpha[2], sArgm[2];
-    const Seg sCk = take((size_t)nseg * n5);
+    // segment storage (stage inputs, chemistry inputs, alpha and argmax) twice: the
+    // recompute of segment sg - 1 on the auxiliary stream overlaps the reverse sweep of sg
+    Seg sS0[2], sS1[2], sS2[2], sX3[2], sApart[2], sAlpha[2], sArgm[2];
+    const Seg sCk = take((size_t)nseg * sn);
     for (int b = 0; b < 2; ++b) {
-        sS0[b] = take((size_t)(K + 1) * n5);
-        sS1[b] = take((size_t)K * n5);
-        sS2[b] = take((size_t)K * n5);
+        sS0[b] = take((size_t)(K + 1) * sn);
+        sS1[b] = take((size_t)K * sn);
+        sS2[b] = take((size_t)K * sn);
+        sX3[b] = take(det ? (size_t)K * sn : 0);
         sApart[b] = take((size_t)nsl * nba * 4);
         sAlpha[b] = take(2 * (size_t)nsl);
         sArgm[b] = take((size_t)nsl);
     }
-    const Seg sLam = take(n5), sLA = take(n5), sLB = take(n5), sAcc = take(n5),
-              sT0 = take(n), sT1 = take(n), sCx = take(50 * nix), sCy = take(50 * niy),
+    const Seg sLam = take(nf), sLA = take(nf), sLB = take(nf), sLC = take(nf), sAcc = take(nf),
+              sT0 = take(n), sT1 = take(n), sCx = take(10 * NU * nix), sCy = take(10 * NU * niy),
               sPart = take(4 * (size_t)nbd + 8), sMisc = take(16), sPc = take(np + 1),
               sPw = take(np + 1), sTerms = take((size_t)N);
     if (tot > c->adj_doubles) {
@@ -1098,9 +1108,11 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     double* S0b[2] = {at(sS0[0]), at(sS0[1])};
     double* S1b[2] = {at(sS1[0]), at(sS1[1])};
     double* S2b[2] = {at(sS2[0]), at(sS2[1])};
+    double* X3b[2] = {at(sX3[0]), at(sX3[1])};
     double* S0 = S0b[0];
     double* S1 = S1b[0];
     double* S2 = S2b[0];
+    double* X3 = X3b[0];
     if (!c->adj_stream) {
         HIPCHK(c, hipStreamCreateWithFlags(&c->adj_stream, hipStreamNonBlocking), "stream");
         for (int q = 0; q < 5; ++q)
@@ -1110,6 +1122,7 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     double* lam = at(sLam);
     double* lA = at(sLA);
     double* lB = at(sLB);
+    double* lC = at(sLC);
     double* acc = at(sAcc);
     double* T0 = at(sT0);
     double* T1 = at(sT1);
@@ -1122,20 +1135,22 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
         HIPCHK(c, hipMemcpyAsync(dpw, pw, sizeof(double) * np, hipMemcpyHostToDevice, s), "probe copy");
     }
     HIPCHK(c, hipMemsetAsync(theta, 0, 2 * sizeof(double), s), "memset");
-    HIPCHK(c, hipMemsetAsync(lam, 0, sizeof(double) * n5, s), "memset");
-    // U0 from the primitives (the Q dependence of E0 is chained at the end)
-    HIPCHK(c, launch_prim_to_cons(ONESTEP, 0, nullptr, ph->gamma, ph->R, ph->Q, n, W0, ck, T0, n, n, s),
-           "init_state");
+    HIPCHK(c, hipMemsetAsync(lam, 0, sizeof(double) * nf, s), "memset");
+    // temperatures of a stored state (detailed model) or the stage scratch (one-step)
+    auto Tof = [&](double* U) { return U + nf; };
+    // U0 from the primitives (the one-step model's Q dependence of E0 is chained at the end)
+    HIPCHK(c, launch_prim_to_cons(model, ns, c->dmech, ph->gamma, ph->R, ph->Q, n, W0, ck,
+                                  det ? Tof(ck) : T0, n, n, s), "init_state");
     double* tdev = misc;   // forward time (unused by fixed dt), misc[1..] scratch
-    const StageArgs base = base_args(P, tm, ck, T0, tdev, nullptr, 0);
+    const StageArgs base = base_args(P, tm, ck, det ? Tof(ck) : T0, tdev, nullptr, 0);
     auto entry = [&](double* U, hipStream_t q) -> hipError_t {
         hipError_t e = launch_clear_reduce(base.red, -1, q);
         if (e == hipSuccess) e = launch_zero_int(P->dstep, q);
         StageArgs a0 = base;
         a0.Uin = U;
-        a0.Tin = T0;
-        a0.Tout = T0;
-        if (e == hipSuccess) e = launch_init(ONESTEP, 0, P->tile_w, a0, q);
+        a0.Tin = det ? Tof(U) : T0;
+        a0.Tout = det ? Tof(U) : T0;
+        if (e == hipSuccess) e = launch_init(model, ns, P->tile_w, a0, q);
         return e;
     };
     auto stage = [&](int stn, double* Un, double* Uin, double* Uout, hipStream_t q) -> hipError_t {
@@ -1144,38 +1159,69 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
         a.U0 = Un;
         a.Uin = Uin;
         a.Uout = Uout;
-        a.Tin = (stn == 2) ? T1 : T0;
-        a.Tout = (stn == 2) ? T0 : T1;
-        if (stn == 3) { a.Tin = T0; a.Tout = T1; }
-        if (stn == 1) { a.Tin = T1; a.Tout = T0; }
-        a.reduce_out = 1;
-        return launch_stage(ONESTEP, 0, P->kind_mask, P->tile_w, a, 0, a.ntiles, q);
+        if (det) {
+            a.Tin = Tof(Uin);
+            a.Tout = Tof(Uout);
+        } else {
+            a.Tin = (stn == 2) ? T1 : T0;
+            a.Tout = (stn == 2) ? T0 : T1;
+            if (stn == 3) { a.Tin = T0; a.Tout = T1; }
+            if (stn == 1) { a.Tin = T1; a.Tout = T0; }
+        }
+        // the detailed model's third stage leaves its maxima to the chemistry step
+        a.reduce_out = (det && stn == 3) ? 0 : 1;
+        return launch_stage(model, ns, P->kind_mask, P->tile_w, a, 0, a.ntiles, q);
+    };
+    // the chemistry step of the detailed model: from the third stage's output X into U
+    auto chemistry = [&](const double* X, double* U, hipStream_t q) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(U, X, sizeof(double) * sn, hipMemcpyDeviceToDevice, q);
+        StageArgs a = base;
+        a.stage = 3;
+        a.Uin = U;
+        a.Uout = U;
+        a.Tin = Tof(U);
+        a.Tout = Tof(U);
+        a.chem_phase = 0;
+        if (e == hipSuccess) e = launch_chem(model, ns, P->tile_w, a, q);
+        return e;
+    };
+    // one full forward step: stage inputs into o1, o2, the chemistry input into x3
+    auto full_step = [&](double* u0, double* o1, double* o2, double* x3, double* nxt,
+                         hipStream_t q) -> hipError_t {
+        hipError_t e = stage(1, u0, u0, o1, q);
+        if (e == hipSuccess) e = stage(2, u0, o1, o2, q);
+        if (det) {
+            if (e == hipSuccess) e = stage(3, u0, o2, x3, q);
+            if (e == hipSuccess) e = chemistry(x3, nxt, q);
+        } else if (e == hipSuccess) {
+            e = stage(3, u0, o2, nxt, q);
+        }
+        return e;
     };
     const double dt = tm->dt_fixed;
     // ---- forward pass with checkpoints; the last segment keeps its stage inputs
     // (it is swept first and needs no recompute)
     const int bl = (nseg - 1) & 1, nl0 = (nseg - 1) * K, ml = N - nl0;
-    double *L0 = S0b[bl], *L1 = S1b[bl], *L2 = S2b[bl];
+    double *L0 = S0b[bl], *L1 = S1b[bl], *L2 = S2b[bl], *L3 = X3b[bl];
     HIPCHK(c, entry(ck, s), "adjoint forward entry");
-    HIPCHK(c, hipMemcpyAsync(T1, T0, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy");
+    if (!det) HIPCHK(c, hipMemcpyAsync(T1, T0, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy");
     double* cur = ck;
     for (int step = 0; step < N; ++step) {
         if (step == nl0 && cur != L0) {
-            HIPCHK(c, hipMemcpyAsync(L0, cur, sizeof(double) * n5, hipMemcpyDeviceToDevice, s), "copy");
+            HIPCHK(c, hipMemcpyAsync(L0, cur, sizeof(double) * sn, hipMemcpyDeviceToDevice, s), "copy");
             cur = L0;
         }
         const int m = step - nl0;
-        double *o1 = S1, *o2 = S2, *nxt;
+        double *o1 = S1, *o2 = S2, *x3 = X3, *nxt;
         if (m >= 0) {
-            o1 = L1 + (size_t)m * n5;
-            o2 = L2 + (size_t)m * n5;
-            nxt = L0 + (size_t)(m + 1) * n5;
+            o1 = L1 + (size_t)m * sn;
+            o2 = L2 + (size_t)m * sn;
+            x3 = L3 + (size_t)m * sn;
+            nxt = L0 + (size_t)(m + 1) * sn;
         } else {
-            nxt = ((step + 1) % K == 0) ? ck + (size_t)((step + 1) / K) * n5 : ((cur == S0) ? S0 + n5 : S0);
+            nxt = ((step + 1) % K == 0) ? ck + (size_t)((step + 1) / K) * sn : ((cur == S0) ? S0 + sn : S0);
         }
-        HIPCHK(c, stage(1, cur, cur, o1, s), "forward stage");
-        HIPCHK(c, stage(2, cur, o1, o2, s), "forward stage");
-        HIPCHK(c, stage(3, cur, o2, nxt, s), "forward stage");
+        HIPCHK(c, full_step(cur, o1, o2, x3, nxt, s), "forward step");
         cur = nxt;
     }
     // ---- reverse sweep
@@ -1183,6 +1229,7 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     A.g = ag;
     A.n = n;
     A.dt = dt;
+    A.mech = c->dmech;
     A.cx = at(sCx);
     A.cy = at(sCy);
     A.part = at(sPart);
@@ -1194,30 +1241,37 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
     AlphaArgs AP{};
     AP.g = ag;
     AP.n = n;
-    AP.step_stride = n5;
+    AP.mech = c->dmech;
+    AP.step_stride = sn;
     AP.nbd = nba;
-    HIPCHK(c, adj_seed_launch(ag, cur, n, dpc, dpw, np, dt, lam, theta, s), "seed");
+    HIPCHK(c, adj_seed_launch(model, ns, ag, c->dmech, cur, n, dpc, dpw, np, dt, lam, theta, s), "seed");
     hipEvent_t evFwd = c->adj_ev[0], evRec[2] = {c->adj_ev[1], c->adj_ev[2]},
                evRev[2] = {c->adj_ev[3], c->adj_ev[4]};
     bool used[2] = {false, false};
     // recompute segment sg (< nseg - 1) into buffer b (auxiliary stream), storing
-    // the three stage inputs of every step, then alpha and its argmax of all of
-    // them and the segment's loss terms
+    // the three stage inputs (and the chemistry input) of every step, then alpha and
+    // its argmax of all of them and the segment's loss terms
     auto recompute = [&](int sg, int b) -> hipError_t {
         const int n0 = sg * K, m1 = std::min(N, n0 + K) - n0;
-        double *R0 = S0b[b], *R1 = S1b[b], *R2 = S2b[b];
+        double *R0 = S0b[b], *R1 = S1b[b], *R2 = S2b[b], *R3 = X3b[b];
         hipError_t e = hipSuccess;
         if (used[b]) e = hipStreamWaitEvent(s2, evRev[b], 0);   // its last reverse sweep is done
         if (e == hipSuccess)
-            e = hipMemcpyAsync(R0, ck + (size_t)sg * n5, sizeof(double) * n5, hipMemcpyDeviceToDevice, s2);
+            e = hipMemcpyAsync(R0, ck + (size_t)sg * sn, sizeof(double) * sn, hipMemcpyDeviceToDevice, s2);
         if (e == hipSuccess) e = entry(R0, s2);
         for (int m = 0; m < m1 && e == hipSuccess; ++m) {
-            double* u0 = R0 + (size_t)m * n5;
-            e = stage(1, u0, u0, R1 + (size_t)m * n5, s2);
-            if (e == hipSuccess) e = stage(2, u0, R1 + (size_t)m * n5, R2 + (size_t)m * n5, s2);
-            // the last step of the segment needs only its first two stage outputs
-            if (e == hipSuccess && m + 1 < m1)
-                e = stage(3, u0, R2 + (size_t)m * n5, R0 + (size_t)(m + 1) * n5, s2);
+            double* u0 = R0 + (size_t)m * sn;
+            double* o1 = R1 + (size_t)m * sn;
+            double* o2 = R2 + (size_t)m * sn;
+            e = stage(1, u0, u0, o1, s2);
+            if (e == hipSuccess) e = stage(2, u0, o1, o2, s2);
+            // the last step of the segment ends at the next checkpoint: the one-step model
+            // needs only its first two stage outputs, the detailed model its chemistry input
+            if (e == hipSuccess && det) e = stage(3, u0, o2, R3 + (size_t)m * sn, s2);
+            if (e == hipSuccess && m + 1 < m1) {
+                if (det) e = chemistry(R3 + (size_t)m * sn, R0 + (size_t)(m + 1) * sn, s2);
+                else e = stage(3, u0, o2, R0 + (size_t)(m + 1) * sn, s2);
+            }
         }
         AlphaArgs ap = AP;
         ap.base[0] = R0;
@@ -1227,11 +1281,11 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
         ap.part = at(sApart[b]);
         ap.alpha = at(sAlpha[b]);
         ap.argm = (int*)at(sArgm[b]);
-        if (e == hipSuccess) e = adj_alpha_launch(ap, s2);
+        if (e == hipSuccess) e = adj_alpha_launch(model, ns, ap, s2);
         // loss terms of states n0 + 1 .. n0 + m1 (the last one is the next checkpoint)
         if (e == hipSuccess)
-            e = adj_loss_launch(ag, R0, n5, m1, ck + (size_t)(sg + 1) * n5, n0, n, dpc, dpw, np, dt,
-                                terms, s2);
+            e = adj_loss_launch(model, ns, ag, c->dmech, R0, sn, m1, ck + (size_t)(sg + 1) * sn, n0, n,
+                                dpc, dpw, np, dt, terms, s2);
         if (e == hipSuccess) e = hipEventRecord(evRec[b], s2);
         return e;
     };
@@ -1244,9 +1298,9 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
         ap.part = at(sApart[bl]);
         ap.alpha = at(sAlpha[bl]);
         ap.argm = (int*)at(sArgm[bl]);
-        HIPCHK(c, adj_alpha_launch(ap, s), "adjoint alpha");
-        HIPCHK(c, adj_loss_launch(ag, L0, n5, ml + 1, nullptr, nl0, n, dpc, dpw, np, dt, terms, s),
-               "loss");
+        HIPCHK(c, adj_alpha_launch(model, ns, ap, s), "adjoint alpha");
+        HIPCHK(c, adj_loss_launch(model, ns, ag, c->dmech, L0, sn, ml + 1, nullptr, nl0, n, dpc, dpw,
+                                  np, dt, terms, s), "loss");
         HIPCHK(c, hipEventRecord(evRec[bl], s), "event");
     }
     HIPCHK(c, hipEventRecord(evFwd, s), "event");
@@ -1256,34 +1310,53 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
         const int n0 = sg * K, m1 = std::min(N, n0 + K) - n0;
         if (sg >= 1) HIPCHK(c, recompute(sg - 1, 1 - b), "recompute");
         HIPCHK(c, hipStreamWaitEvent(s, evRec[b], 0), "event");
-        double *R0 = S0b[b], *R1 = S1b[b], *R2 = S2b[b];
+        double *R0 = S0b[b], *R1 = S1b[b], *R2 = S2b[b], *R3 = X3b[b];
         const double* alpha = at(sAlpha[b]);
         const int* argm = (const int*)at(sArgm[b]);
         for (int m = m1 - 1; m >= 0; --m) {
+            double* lw3 = lam;
+            if (det) {   // the chemistry step: U^{n+1} = C(U*), U* = the third stage's output
+                AdjChemArgs ac{};
+                ac.n = n;
+                ac.mech = c->dmech;
+                ac.Ustar = R3 + (size_t)m * sn;
+                ac.Tstar = Tof(R3 + (size_t)m * sn);
+                ac.lamIn = lam;
+                ac.lamOut = lC;
+                ac.dt = dt;
+                ac.status = c->dstatus;
+                HIPCHK(c, adj_chem_launch(ns, ac, s), "adjoint chemistry");
+                lw3 = lC;
+            }
             AdjArgs a3 = A;   // stage 3: W = U/3 + 2/3 (V + dt L(V)), V = U^(2)
-            a3.V = R2 + (size_t)m * n5; a3.lamW = lam; a3.lamOut = lA; a3.acc = acc;
+            a3.V = R2 + (size_t)m * sn; a3.VT = det ? Tof(R2 + (size_t)m * sn) : nullptr;
+            a3.lamW = lw3; a3.lamOut = lA; a3.acc = acc;
             a3.b = 2.0 / 3.0; a3.a = 1.0 / 3.0; a3.init_acc = 1; a3.add_out = 0;
             a3.alpha = alpha + 2 * (3 * m + 2); a3.argm = argm + 2 * (3 * m + 2);
-            HIPCHK(c, adj_stage(a3, s), "adjoint stage 3");
+            HIPCHK(c, adj_stage(model, ns, a3, s), "adjoint stage 3");
             AdjArgs a2 = A;   // stage 2: W = 3/4 U + 1/4 (V + dt L(V)), V = U^(1)
-            a2.V = R1 + (size_t)m * n5; a2.lamW = lA; a2.lamOut = lB; a2.acc = acc;
+            a2.V = R1 + (size_t)m * sn; a2.VT = det ? Tof(R1 + (size_t)m * sn) : nullptr;
+            a2.lamW = lA; a2.lamOut = lB; a2.acc = acc;
             a2.b = 0.25; a2.a = 0.75; a2.init_acc = 0; a2.add_out = 0;
             a2.alpha = alpha + 2 * (3 * m + 1); a2.argm = argm + 2 * (3 * m + 1);
-            HIPCHK(c, adj_stage(a2, s), "adjoint stage 2");
+            HIPCHK(c, adj_stage(model, ns, a2, s), "adjoint stage 2");
             AdjArgs a1 = A;   // stage 1: W = V + dt L(V), V = U^n; then the loss seed of U^n
-            a1.V = R0 + (size_t)m * n5; a1.lamW = lB; a1.lamOut = lA; a1.acc = acc;
+            a1.V = R0 + (size_t)m * sn; a1.VT = det ? Tof(R0 + (size_t)m * sn) : nullptr;
+            a1.lamW = lB; a1.lamOut = lA; a1.acc = acc;
             a1.b = 1.0; a1.a = 0.0; a1.init_acc = 0; a1.add_out = 1;
             a1.alpha = alpha + 2 * (3 * m); a1.argm = argm + 2 * (3 * m);
-            a1.seedU = (n0 + m >= 1) ? R0 + (size_t)m * n5 : nullptr;
-            HIPCHK(c, adj_stage(a1, s), "adjoint stage 1");
+            a1.seedU = (n0 + m >= 1) ? R0 + (size_t)m * sn : nullptr;
+            a1.seedT = (det && a1.seedU) ? Tof(R0 + (size_t)m * sn) : nullptr;
+            HIPCHK(c, adj_stage(model, ns, a1, s), "adjoint stage 1");
             std::swap(lam, acc);
         }
         HIPCHK(c, hipEventRecord(evRev[b], s), "event");
         used[b] = true;
     }
     HIPCHK(c, adj_loss_sum_launch(terms, N, loss, s), "loss");
-    // chain dL/dU0 to the primitives; E0 = p/(gamma-1) + rho |u|^2/2 + rho Y Q adds to dL/dQ
-    HIPCHK(c, adj_chain_launch(ag, W0, lam, n, gW, A.part, theta, s), "chain");
+    // chain dL/dU0 to the primitives; the one-step model's E0 = p/(gamma-1) + rho |u|^2/2 +
+    // rho Y Q adds to dL/dQ
+    HIPCHK(c, adj_chain_launch(model, ns, ag, c->dmech, W0, lam, n, gW, A.part, theta, s), "chain");
     return JANC_OK;
 }
 

@@ -153,29 +153,33 @@ __device__ __forceinline__ void halo_prims(const double (&u)[NU], double T, cons
     }
 }
 
-// Newton for T from the internal energy on mixture NASA coefficients
-// (Y fixed during the solve, so the species sums are formed once). With two
-// NASA-7 ranges (one t_mid for all species) both mixture sets are formed and
-// each iteration uses the set of the current T.
+// Mixture NASA-7 coefficients (Y fixed, so the species sums are formed once): per mass,
+// sum_k Y_k R_k a_q of each range, and R_mix. With two NASA-7 ranges (one t_mid for all
+// species) both sets are formed and an evaluation uses the set of its temperature.
+struct MixNasa {
+    double b[6], h[6];
+    double Rmix, tm;
+    bool two;
+};
+
 template <int NS>
-__device__ __forceinline__ unsigned newton_T(const double (&Y)[NS], double e, CMech* m,
-                                             double& T, double& cv, double& Rmix) {
+__device__ __forceinline__ void mix_nasa(const double (&Y)[NS], CMech* m, MixNasa& x) {
     double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0, b4 = 0.0, b5 = 0.0;
     double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0, h4 = 0.0, h5 = 0.0;
-    const bool two = m->two_range != 0;
-    const double tm = m->tmid[0];
-    Rmix = 0.0;
+    x.two = m->two_range != 0;
+    x.tm = m->tmid[0];
+    x.Rmix = 0.0;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         const double w = Y[k] * m->Rk[k];
-        Rmix += w;
+        x.Rmix += w;
         b0 += w * m->nasa[k][0];
         b1 += w * m->nasa[k][1];
         b2 += w * m->nasa[k][2];
         b3 += w * m->nasa[k][3];
         b4 += w * m->nasa[k][4];
         b5 += w * m->nasa[k][5];
-        if (two) {
+        if (x.two) {
             h0 += w * m->nasa_hi[k][0];
             h1 += w * m->nasa_hi[k][1];
             h2 += w * m->nasa_hi[k][2];
@@ -184,20 +188,32 @@ __device__ __forceinline__ unsigned newton_T(const double (&Y)[NS], double e, CM
             h5 += w * m->nasa_hi[k][5];
         }
     }
-    // e(T) and cv(T) of the mixture at T
-    auto eval = [&](double Tc, double& ec, double& cvv) {
-        const bool hi = two && Tc >= tm;
-        const double B0 = hi ? h0 : b0, B1 = hi ? h1 : b1, B2 = hi ? h2 : b2, B3 = hi ? h3 : b3,
-                     B4 = hi ? h4 : b4, B5 = hi ? h5 : b5;
-        const double c0 = B0 - Rmix, c1 = 0.5 * B1, c2 = B2 * (1.0 / 3.0), c3 = 0.25 * B3,
-                     c4 = 0.2 * B4;
-        ec = Tc * (c0 + Tc * (c1 + Tc * (c2 + Tc * (c3 + Tc * c4)))) + B5;
-        cvv = c0 + Tc * (B1 + Tc * (B2 + Tc * (B3 + Tc * B4)));
-    };
+    x.b[0] = b0; x.b[1] = b1; x.b[2] = b2; x.b[3] = b3; x.b[4] = b4; x.b[5] = b5;
+    x.h[0] = h0; x.h[1] = h1; x.h[2] = h2; x.h[3] = h3; x.h[4] = h4; x.h[5] = h5;
+}
+
+// e(T) and cv(T) of the mixture (per mass).
+__device__ __forceinline__ void mix_eval(const MixNasa& x, double Tc, double& ec, double& cvv) {
+    const bool hi = x.two && Tc >= x.tm;
+    const double B0 = hi ? x.h[0] : x.b[0], B1 = hi ? x.h[1] : x.b[1], B2 = hi ? x.h[2] : x.b[2],
+                 B3 = hi ? x.h[3] : x.b[3], B4 = hi ? x.h[4] : x.b[4], B5 = hi ? x.h[5] : x.b[5];
+    const double c0 = B0 - x.Rmix, c1 = 0.5 * B1, c2 = B2 * (1.0 / 3.0), c3 = 0.25 * B3,
+                 c4 = 0.2 * B4;
+    ec = Tc * (c0 + Tc * (c1 + Tc * (c2 + Tc * (c3 + Tc * c4)))) + B5;
+    cvv = c0 + Tc * (B1 + Tc * (B2 + Tc * (B3 + Tc * B4)));
+}
+
+// Newton for T from the internal energy on the mixture coefficients (Sec. 4.2).
+template <int NS>
+__device__ __forceinline__ unsigned newton_T(const double (&Y)[NS], double e, CMech* m,
+                                             double& T, double& cv, double& Rmix) {
+    MixNasa x;
+    mix_nasa<NS>(Y, m, x);
+    Rmix = x.Rmix;
     unsigned st = STB_NEWTON;
     for (int it = 0; it < 50; ++it) {
         double ec, cvv;
-        eval(T, ec, cvv);
+        mix_eval(x, T, ec, cvv);
         const double dT = (ec - e) / cvv;
         T -= dT;
         if (!(fabs(dT) <= 1e-12 * fabs(T))) {
@@ -208,7 +224,7 @@ __device__ __forceinline__ unsigned newton_T(const double (&Y)[NS], double e, CM
         break;
     }
     double ec;
-    eval(T, ec, cv);
+    mix_eval(x, T, ec, cv);
     return st;
 }
 

@@ -159,8 +159,10 @@ hipError_t launch_prim_to_cons(int model, int ns, const DevMech* mech, double ga
 bool model_supported(int model, int ns);
 
 
-// Discrete adjoint (uniform grid, one-step model): grid constants and the
-// arguments of one stage's reverse sweep.
+// Discrete adjoint (uniform grid; one-step and detailed models): grid constants and
+// the arguments of one stage's reverse sweep. A stored state of the detailed model
+// is [NU][n] conserved fields followed by [n] temperatures (the Newton solution the
+// forward stored with it); one-step states are [NU][n].
 struct AdjGrid {
     int nx, ny, twod, pad;
     int bc[4];
@@ -173,19 +175,22 @@ struct AdjGrid {
 struct AdjArgs {
     AdjGrid g;
     long long n;              // cells
-    const double* V;          // stage input [5][n]
-    const double* lamW;       // adjoint of the stage output [5][n]
-    double* lamOut;           // adjoint of the stage input [5][n]
-    double* acc;              // adjoint of the step start U^n [5][n]
+    const double* V;          // stage input [NU][n]
+    const double* VT;         // its temperatures [n] (detailed model)
+    const DevMech* mech;      // detailed model: the mechanism
+    const double* lamW;       // adjoint of the stage output [NU][n]
+    double* lamOut;           // adjoint of the stage input [NU][n]
+    double* acc;              // adjoint of the step start U^n [NU][n]
     double b, a, dt;
     int init_acc, add_out;
-    double *cx, *cy;          // reverse WENO5 weights per interface [5][10][interfaces]
+    double *cx, *cy;          // reverse WENO5 weights per interface [NU][10][interfaces]
     const double* alpha;      // [2] alpha_x, alpha_y of the stage input
     const int* argm;          // [2] lowest cell attaining them
     double* part;             // [nbd][4] block partials
     int nbd;                  // cell blocks
     double* theta;            // [2]: dL/dQ, dL/dEa
     const double* seedU;      // state whose probe loss seeds acc after this stage (or null)
+    const double* seedT;      // its temperatures (detailed model)
     const int* pc;
     const double* pw;
     int np;
@@ -196,7 +201,8 @@ struct AdjArgs {
 struct AlphaArgs {
     AdjGrid g;
     long long n;
-    const double* base[3];
+    const DevMech* mech;
+    const double* base[3];    // (detailed model: temperatures at base + NU n)
     long long step_stride;
     int nsteps;
     int nbd;
@@ -205,16 +211,63 @@ struct AlphaArgs {
     int* argm;                // [slices][2]
 };
 
-hipError_t adj_alpha_launch(const AlphaArgs& P, hipStream_t s);
-hipError_t adj_stage(const AdjArgs& A, hipStream_t s);
-hipError_t adj_loss_launch(const AdjGrid& g, const double* base, long long stride, int count,
-                           const double* last, int n0, long long n, const int* pc, const double* pw,
-                           int np, double dt, double* term, hipStream_t s);
+// Chemistry step of the detailed model in reverse (one launch, one cell per thread):
+// lam (adjoint of the step's output U^{n+1}) becomes the adjoint of its input U*
+// (the third stage's output, at temperature Tstar).
+struct AdjChemArgs {
+    long long n;
+    const DevMech* mech;
+    const double* Ustar;      // [NU][n]
+    const double* Tstar;      // [n]
+    const double* lamIn;      // adjoint of U^{n+1} [NU][n]
+    double* lamOut;           // adjoint of U* [NU][n]
+    double dt;
+    unsigned* status;
+};
+
+// model: ONESTEP or DETAILED; ns: species of the detailed model (2 or 9)
+hipError_t adj_alpha_launch(int model, int ns, const AlphaArgs& P, hipStream_t s);
+hipError_t adj_stage(int model, int ns, const AdjArgs& A, hipStream_t s);
+hipError_t adj_chem_launch(int ns, const AdjChemArgs& A, hipStream_t s);
+hipError_t adj_loss_launch(int model, int ns, const AdjGrid& g, const DevMech* mech,
+                           const double* base, long long stride, int count, const double* last,
+                           int n0, long long n, const int* pc, const double* pw, int np, double dt,
+                           double* term, hipStream_t s);
 hipError_t adj_loss_sum_launch(const double* term, int nsteps, double* loss, hipStream_t s);
-hipError_t adj_seed_launch(const AdjGrid& g, const double* U, long long n, const int* pc,
-                           const double* pw, int np, double dt, double* lam, double* theta,
-                           hipStream_t s);
-hipError_t adj_chain_launch(const AdjGrid& g, const double* W, const double* lam, long long n,
-                            double* gW, double* part, double* theta, hipStream_t s);
+hipError_t adj_seed_launch(int model, int ns, const AdjGrid& g, const DevMech* mech,
+                           const double* U, long long n, const int* pc, const double* pw, int np,
+                           double dt, double* lam, double* theta, hipStream_t s);
+hipError_t adj_chain_launch(int model, int ns, const AdjGrid& g, const DevMech* mech,
+                            const double* W, const double* lam, long long n, double* gW,
+                            double* part, double* theta, hipStream_t s);
+
+// Launches of the detailed model for one species count NS (janc_species.hip, one
+// translation unit per count): the step's kernels and the adjoint's.
+struct SpeciesOps {
+    int ns;
+    hipError_t (*stage)(int kind_mask, int tile_w, const StageArgs& a, int first_tile, int ntiles,
+                        int owner, hipStream_t s);
+    hipError_t (*init)(const StageArgs& a, hipStream_t s);
+    hipError_t (*chem)(const StageArgs& a, hipStream_t s);
+    hipError_t (*restrict_fine)(const StageArgs& a, const int* fine_blocks, int nfine, hipStream_t s);
+    hipError_t (*ring_fill)(const StageArgs& a, const int* ring_blocks, int nring, hipStream_t s);
+    hipError_t (*prim_to_cons)(const DevMech* mech, long long n, const double* W, double* U, double* T,
+                               long long stride_in, long long stride_out, hipStream_t s);
+    hipError_t (*adj_alpha)(const AlphaArgs& P, hipStream_t s);     // before adj_alpha_reduce
+    hipError_t (*adj_stage)(const AdjArgs& A, hipStream_t s);
+    hipError_t (*adj_chem)(const AdjChemArgs& A, hipStream_t s);
+    hipError_t (*adj_loss)(const AdjGrid& g, const DevMech* mech, const double* base, long long stride,
+                           int count, const double* last, int n0, long long n, const int* pc,
+                           const double* pw, int np, double dt, double* term, hipStream_t s);
+    hipError_t (*adj_seed)(const AdjGrid& g, const DevMech* mech, const double* U, long long n,
+                           const int* pc, const double* pw, int np, double dt, double* lam,
+                           double* theta, hipStream_t s);
+    hipError_t (*adj_chain)(const AdjGrid& g, const DevMech* mech, const double* W, const double* lam,
+                            long long n, double* gW, double* part, hipStream_t s);   // before adj_chain_sum
+};
+
+// Species counts with compiled kernels: JANC_NS_FIRST .. JANC_NS_LAST (all of them).
+constexpr int JANC_NS_FIRST = 2, JANC_NS_LAST = MAXS;
+const SpeciesOps* species_ops(int ns);   // null: no kernels for this count
 
 }  // namespace janc
