@@ -78,16 +78,23 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per stage-kernel launch from the committed FETCH_SIZE / WRITE_SIZE
-    counter passes (profiles/), or None when the kernel sources changed since."""
+def measured_traffic(width, linear):
+    """HBM bytes per stage-kernel launch of the schedule (tile width, workgroup order) from
+    the committed FETCH_SIZE / WRITE_SIZE counter passes (profiles/, one line per
+    schedule: source hash, width, order, bytes), or None when the kernel sources changed
+    since or the schedule was not measured."""
     path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.txt")
+    order = "linear" if linear else "xcd"
     try:
         with open(path) as fh:
-            hsh, val = fh.read().split()
+            for line in fh:
+                f = line.split()
+                if len(f) == 4 and f[0] == kernel_source_hash() and int(f[1]) == width \
+                        and f[2] == order:
+                    return float(f[3])
     except (OSError, ValueError):
         return None
-    return float(val) if hsh == kernel_source_hash() else None
+    return None
 
 
 def optional(name, fn):
@@ -167,9 +174,18 @@ def main():
     ap.add_argument("--paper-shape", action="store_true",
                     help="also time the uniform 9-species path on a 4000 x 1000 grid, the shape "
                          "of the paper's single-GPU core-solver run (context only)")
+    ap.add_argument("--schedule", default=None, metavar="WIDTH/ORDER",
+                    help="fix the stage launch shape instead of autotuning it, e.g. 32/xcd or "
+                         "16/linear (counter passes)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
+    fixed = None
+    if args.schedule is not None:
+        w, _, o = args.schedule.partition("/")
+        if w not in ("16", "32", "64") or o not in ("xcd", "linear"):
+            ap.error("--schedule takes WIDTH/ORDER with WIDTH 16, 32 or 64 and ORDER xcd or linear")
+        fixed = (int(w), int(o == "linear"))
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
@@ -238,18 +254,26 @@ def main():
     default_value = cells * 3 * args.steps / d_s
     log(f"[bench] default shape: {1e3 * d_s / args.steps:.3f} ms/step, {default_value:.4e} cell-stage/s")
     plan = ctx.plan(domains, case.blocks, case.pool_cells, janc.PLAN_DEFAULT)
-    U0, T0, _ = fresh_state()
-    choice, cand_ms = plan.autotune(tm, U0, T0, reps=5)
-    del U0, T0
-    log(f"[bench] autotuner: tile width {choice[0]}, {'linear' if choice[1] else 'XCD-contiguous'} "
-        f"order; candidates (ms per first-stage launch) "
-        + ", ".join(f"{w}/{'lin' if l else 'xcd'} {v:.3f}" for (w, l), v in cand_ms.items()))
+    if fixed is None:
+        U0, T0, _ = fresh_state()
+        choice, cand_ms = plan.autotune(tm, U0, T0, reps=5)
+        del U0, T0
+        log(f"[bench] autotuner: tile width {choice[0]}, "
+            f"{'linear' if choice[1] else 'XCD-contiguous'} order; candidates (ms per "
+            f"first-stage launch) "
+            + ", ".join(f"{w}/{'lin' if l else 'xcd'} {v:.3f}" for (w, l), v in cand_ms.items()))
+    else:
+        choice, cand_ms = fixed, {}
+        plan.set_schedule(*fixed)
+        log(f"[bench] fixed schedule: tile width {fixed[0]}, "
+            f"{'linear' if fixed[1] else 'XCD-contiguous'} order")
     sim_sync = []
     gpu_s, wall_s, (U, T, t) = timed_run(plan, args.steps, args.warmup, sim_sync)
     value = cells * 3 * args.steps / gpu_s
     ms_step = 1e3 * gpu_s / args.steps
     log(f"[bench] {ms_step:.3f} ms/step, {value:.4e} cell-stage/s (wall {wall_s:.3f} s)")
     autotune = {"tile_width": choice[0], "order": "linear" if choice[1] else "xcd-contiguous",
+                "fixed": fixed is not None,
                 "candidates_ms": {f"{w}/{'linear' if l else 'xcd'}": v for (w, l), v in cand_ms.items()},
                 "default_shape_value": default_value, "gain_over_default": value / default_value}
 
@@ -605,7 +629,7 @@ def main():
             "peak": PEAK_FP64_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tf / PEAK_FP64_VALU_TFLOPS,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(*choice),
             "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
             "flops_per_cell_stage": stage_flops(2, nU, True),
             "solved_cells_per_launch": solved,

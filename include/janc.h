@@ -203,8 +203,11 @@ enum {
     JANC_PLAN_CROSSOVER = 4,   /* crossover advance (Fig. 2a, Alg. 2) instead of the synchronous one */
     JANC_PLAN_PER_LEVEL = 8,   /* one stage launch per refinement level (comparison form: the
                                   paper's per-level batching of equal-shape blocks, Alg. 2) */
-    JANC_PLAN_AUTOTUNE = 16    /* the first janc_step_blocks call runs janc_plan_autotune on its
+    JANC_PLAN_AUTOTUNE = 16,   /* the first janc_step_blocks call runs janc_plan_autotune on its
                                   input state (5 timed launches per candidate) before stepping */
+    JANC_PLAN_RESOLVE_HALOS = 32  /* no halo source table: the stage kernel looks up every
+                                  off-block or coarse-fine ring source itself (comparison form;
+                                  also the form of plans whose pool has 2^28 cells or more) */
 };
 
 /* Validate a block table and build its device work lists (blocks, level maps,
@@ -235,7 +238,9 @@ janc_status janc_plan_set_schedule(janc_plan *plan, int tile_width, int linear);
  * workgroup orders of janc_plan_set_schedule; 1-D-only plans: the two orders -- over
  * `reps` (1..1000) first-stage launches on the state U, T (device, read only; only the
  * plan's workspaces are written), with HIP events on `stream`, and keeps the fastest in
- * the plan (synchronous on the host). choice (host [2], may be NULL) receives the tile
+ * the plan (synchronous on the host); a linear-order candidate's time is charged 3 %
+ * extra, since that order reads 2-3x the HBM bytes and ties between the orders are
+ * timing noise. choice (host [2], may be NULL) receives the tile
  * width and the order; ms (host [6], may be NULL) the median launch time of each
  * candidate in the order (16, XCD), (16, linear), (32, XCD), (32, linear), (64, XCD),
  * (64, linear), -1 where not timed. Every candidate gives bitwise the same results. */

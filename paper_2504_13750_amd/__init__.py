@@ -38,6 +38,7 @@ CPG, ONESTEP, DETAILED = 0, 1, 2
 BC_PERIODIC, BC_ZEROGRAD, BC_SLIPWALL, BC_DIRICHLET = 0, 1, 2, 3
 PLAN_DEFAULT, PLAN_PER_BLOCK, PLAN_NO_GRAPH, PLAN_CROSSOVER, PLAN_PER_LEVEL = 0, 1, 2, 4, 8
 PLAN_AUTOTUNE = 16
+PLAN_RESOLVE_HALOS = 32
 AUTOTUNE_CANDIDATES = [(16, 0), (16, 1), (32, 0), (32, 1), (64, 0), (64, 1)]
 SPLIT_LIE, SPLIT_STRANG = 0, 1
 JAC_FROZEN_T, JAC_FULL = 0, 1

@@ -887,14 +887,16 @@ __global__ __launch_bounds__(AWG) void adj_chem(AdjChemArgs A) {
             if (ar > amax) { amax = ar; p = r; }
         }
         piv[col] = p;
+        if (__any(p != col)) {   // row exchange by selects, where some cell needs one
 #pragma unroll
-        for (int r = col + 1; r < NT; ++r) {
-            const bool sw = (r == p);
+            for (int r = col + 1; r < NT; ++r) {
+                const bool sw = (r == p);
 #pragma unroll
-            for (int q = 0; q < NT; ++q) {
-                const double top = J[col][q], row = J[r][q];
-                J[col][q] = sw ? row : top;
-                J[r][q] = sw ? top : row;
+                for (int q = 0; q < NT; ++q) {
+                    const double top = J[col][q], row = J[r][q];
+                    J[col][q] = sw ? row : top;
+                    J[r][q] = sw ? top : row;
+                }
             }
         }
         const double pv = J[col][col];

@@ -91,6 +91,8 @@ struct janc_plan {
     DevBlock* dblk = nullptr;
     int* dmap = nullptr;
     Tile* dtiles = nullptr;
+    int* dhsrc = nullptr;          // halo source table (StageArgs::hsrc), or null
+    int hstride = 0;
     double* ddir = nullptr;
     unsigned long long* dred = nullptr;
     int red_stride = 0;
@@ -179,8 +181,8 @@ void plan_free(janc_plan* p) {
     if (p->graph) hipGraphDestroy(p->graph);
     if (p->gdone) hipEventDestroy(p->gdone);
     if (!p->arena) {
-        void* ptrs[] = {p->ddom, p->dblk, p->dmap, p->dtiles, p->ddir, p->dred, p->ddt, p->dstep,
-                        p->dfine, p->dring, p->U1, p->U2, p->T1, p->T2};
+        void* ptrs[] = {p->ddom, p->dblk, p->dmap, p->dtiles, p->dhsrc, p->ddir, p->dred, p->ddt,
+                        p->dstep, p->dfine, p->dring, p->U1, p->U2, p->T1, p->T2};
         for (void* q : ptrs)
             if (q) hipFree(q);
     }
@@ -289,7 +291,7 @@ janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, con
     P->arena = arena;
     P->arena_cap = arena_cap;
     if (flags & ~(JANC_PLAN_PER_BLOCK | JANC_PLAN_NO_GRAPH | JANC_PLAN_CROSSOVER | JANC_PLAN_PER_LEVEL |
-                  JANC_PLAN_AUTOTUNE))
+                  JANC_PLAN_AUTOTUNE | JANC_PLAN_RESOLVE_HALOS))
         return fail(c, JANC_EINVAL, "unknown plan flags");
     if ((flags & JANC_PLAN_PER_BLOCK) && (flags & JANC_PLAN_CROSSOVER))
         return fail(c, JANC_EINVAL, "the crossover advance has no per-block form");
@@ -528,6 +530,37 @@ janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, con
 
 // Tiles of every valid block for the plan's 2-D tile width (1-D blocks: 256-cell rows),
 // grouped by level (the crossover advance launches one level at a time).
+StageArgs base_args(janc_plan* P, const janc_time* tm, double* U, double* T, double* t,
+                    double* dt_log, int cap);
+
+// Halo source table: for every tile point outside its block or on a coarse-fine ring,
+// the source resolve() gives (level map, block record, coarser level), found once per
+// plan by a kernel so that the stage launches read one word per such point. Plans of
+// the allocation-free entry point, plans flagged JANC_PLAN_RESOLVE_HALOS and pools of
+// 2^28 cells or more (8 * cell + flags must fit an int) keep resolving in the kernel.
+janc_status build_halo_table(janc_ctx* c, janc_plan* P) {
+    if (P->dhsrc && !P->arena) hipFree(P->dhsrc);
+    P->dhsrc = nullptr;
+    P->hstride = 0;
+    if (P->arena || (P->flags & JANC_PLAN_RESOLVE_HALOS) || P->pool >= (1ll << 28) || P->htiles.empty())
+        return JANC_OK;
+    const int stride = halo_table_stride(P->tile_w, P->kind_mask);
+    int* tab = nullptr;
+    if (janc_status st = dalloc(c, &tab, (size_t)P->htiles.size() * stride)) return st;
+    janc_time tm{};
+    tm.cfl = 1.0;
+    StageArgs a = base_args(P, &tm, nullptr, nullptr, nullptr, nullptr, 0);
+    hipError_t e = launch_halo_table(P->tile_w, a, tab, stride, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        hipFree(tab);
+        return hipfail(c, e, "halo table");
+    }
+    P->dhsrc = tab;
+    P->hstride = stride;
+    return JANC_OK;
+}
+
 janc_status build_tiles(janc_ctx* c, janc_plan* P) {
     P->htiles.clear();
     P->tile_first.assign(P->nblk, 0);
@@ -556,7 +589,8 @@ janc_status build_tiles(janc_ctx* c, janc_plan* P) {
     }
     if (P->dtiles && !P->arena) hipFree(P->dtiles);
     P->dtiles = nullptr;
-    return pupload(P, &P->dtiles, P->htiles);
+    if (janc_status st = pupload(P, &P->dtiles, P->htiles)) return st;
+    return build_halo_table(c, P);
 }
 
 StageArgs base_args(janc_plan* P, const janc_time* tm, double* U, double* T, double* t,
@@ -583,6 +617,8 @@ StageArgs base_args(janc_plan* P, const janc_time* tm, double* U, double* T, dou
     a.full_jac = (tm->jac == JANC_JAC_FULL && P->ctx->model == DETAILED) ? 1 : 0;
     a.status = P->ctx->dstatus;
     a.linear_sched = P->linear_sched;
+    a.hsrc = P->dhsrc;
+    a.hstride = P->hstride;
     if (P->flags & JANC_PLAN_CROSSOVER) {
         a.cross = 1;
         a.xlevels = P->maxlev + 1;
@@ -755,9 +791,15 @@ void drop_graph(janc_plan* P) {
 // Autotuner of the stage launch: each candidate (2-D tile width 16, 32 or 64 --
 // 16 x 16, 32 x 8, 64 x 4 cells -- and the tile order of the workgroups) is timed
 // with HIP events over `reps` first-stage launches of the plan on the state (U, T);
-// the fastest is kept in the plan. Only the plan's own workspaces are written (the
-// first stage's output goes to the stage buffer), and every candidate computes the
-// same result bitwise, so the choice changes speed only.
+// the fastest is kept in the plan. The linear order reads 2 to 3 times the HBM bytes
+// of the XCD-contiguous order (halo rows shared by neighbouring tiles are fetched
+// once per XCD L2 instead of once per tile); on an ALU-bound launch the two times
+// differ by noise, so a linear-order candidate is charged LINEAR_HANDICAP on its time
+// and wins only when it is clearly faster. Only the plan's own workspaces are written
+// (the first stage's output goes to the stage buffer), and every candidate computes
+// the same result bitwise, so the choice changes speed only.
+constexpr double LINEAR_HANDICAP = 1.03;
+
 janc_status autotune(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U, double* T, int reps,
                      double* ms_out, hipStream_t s) {
     HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
@@ -819,8 +861,9 @@ janc_status autotune(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U, 
         std::sort(times.begin(), times.end());
         const double med = times.empty() ? INFINITY : times[times.size() / 2];
         if (ms_out) ms_out[k] = med;
-        if (med < best) {
-            best = med;
+        const double charged = cands[k].lin ? med * LINEAR_HANDICAP : med;
+        if (charged < best) {
+            best = charged;
             bw = cands[k].w;
             bl = cands[k].lin;
         }

@@ -127,6 +127,11 @@ struct StageArgs {
     unsigned long long* xred; // all levels' slot sets (level l at l * RED_BUFS * red.stride)
     const double* Tbase;      // T of the pool (coarser levels' current state)
     int linear_sched;         // stage launches: workgroup b takes tile b (else XCD-contiguous runs)
+    // halo source table of the plan (or null: the stage kernel resolves every source):
+    // entry [tile * hstride + point] = 8 * source + flags for each point whose source is
+    // not its own block's cell at that position
+    const int* hsrc;
+    int hstride;
 };
 
 // Layer update: a candidate subregion (layer-`lev` cells) and a fill job.
@@ -144,6 +149,9 @@ hipError_t launch_zero_int(int* p, hipStream_t s);
 hipError_t launch_stage(int model, int ns, int kind_mask, int tile_w, const StageArgs& a,
                         int first_tile, int ntiles, hipStream_t s);
 hipError_t launch_init(int model, int ns, int tile_w, const StageArgs& a, hipStream_t s);
+// Halo source table (row stride: the largest point count of the tile kinds in kind_mask)
+int halo_table_stride(int tile_w, int kind_mask);
+hipError_t launch_halo_table(int tile_w, const StageArgs& a, int* out, int stride, hipStream_t s);
 hipError_t launch_chem(int model, int ns, int tile_w, const StageArgs& a, hipStream_t s);
 hipError_t launch_restrict(int model, int ns, const StageArgs& a, const int* fine_blocks,
                            int nfine, hipStream_t s);

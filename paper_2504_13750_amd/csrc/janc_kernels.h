@@ -75,8 +75,23 @@ struct Geom {
     }
 };
 
+// Point p of a tile of tw x th valid cells: its tile-local position and whether the x
+// and the y sweep read it (the halo is cross-shaped).
+template <int TX, int TY>
+__device__ __forceinline__ void point_needs(int p, int tw, int th, int& li, int& lj, bool& nx,
+                                            bool& ny) {
+    Geom<TX, TY>::point(p, li, lj);
+    nx = (lj >= 0 && lj < th) && (li >= -3 && li < tw + 3);
+    ny = Geom<TX, TY>::TWO && (li >= 0 && li < tw) && (lj >= -3 && lj < th + 3);
+}
+
+// Block-local cell (bi, bj) is its own source: inside the block and not a ring cell.
+__device__ __forceinline__ bool own_source(const DevBlock& B, int bi, int bj) {
+    return bi >= 0 && bi < B.nx && bj >= 0 && bj < B.ny && !ring_at(B, bi, bj);
+}
+
 template <int M, int NU, int TX, int TY>
-__device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
+__device__ void stage_tile(const StageArgs& a, const int ti, const Tile tile, double* smem) {
     using G = Geom<TX, TY>;
     static_assert(TX * TY == WG, "one owned cell per thread");
     // set k at smem + k * SET: F+ / F- of x (fpx, fmx) and y (fpy, fmy), the WENO5 of
@@ -115,21 +130,26 @@ __device__ void stage_tile(const StageArgs& a, const Tile tile, double* smem) {
         vxr[q] = vyr[q] = pr[q] = 0.0;
 #pragma unroll
         for (int f = 0; f < NU; ++f) ur[q][f] = 0.0;
+        // the table word is loaded for every point (one coalesced row per tile) ahead of
+        // the test that decides whether it is used
+        const int hv = (a.hsrc && p < G::NP) ? a.hsrc[(size_t)ti * a.hstride + p] : 0;
         if (p < G::NP) {
             int li, lj;
-            G::point(p, li, lj);
-            needx[q] = (lj >= 0 && lj < th) && (li >= -3 && li < tw + 3);
-            needy[q] = G::TWO && (li >= 0 && li < tw) && (lj >= -3 && lj < th + 3);
+            point_needs<TX, TY>(p, tw, th, li, lj, needx[q], needy[q]);
             xoff[q] = lj * G::PW + li + 3;
             yoff[q] = (lj + 3) * TX + li;
             if (needx[q] || needy[q]) {
                 const int bi = tile.x0 + li, bj = tile.y0 + lj;
                 long long src;
                 unsigned fl = 0u;
-                if (bi >= 0 && bi < B.nx && bj >= 0 && bj < B.ny && !ring_at(B, bi, bj))
+                if (own_source(B, bi, bj)) {
                     src = B.offset + (long long)bj * B.nx + bi;
-                else
+                } else if (a.hsrc) {
+                    src = (long long)(hv >> 3);
+                    fl = (unsigned)(hv & 7);
+                } else {
                     src = resolve(a, D, lev, B.i0 + bi, B.j0 + bj, fl);
+                }
                 double T;
                 // crossover: coarser levels are read at their current state
                 const bool base = a.cross && (fl & 4u);
@@ -309,17 +329,51 @@ __global__ __launch_bounds__(WG, STAGE_WAVES) void stage_kernel(StageArgs a, int
     constexpr int L2 = Geom<TX, TY>::LDS, L1 = Geom<WG, 1>::LDS;
     __shared__ double smem[(L2 > L1) ? L2 : L1];
     if (blockIdx.x == 0) stage_bookkeeping(a, owner_launch);
-    const Tile tile = a.tiles[first_tile + (a.linear_sched ? (int)blockIdx.x
-                                                           : xcd_chunk(blockIdx.x, gridDim.x))];
+    const int ti = first_tile + (a.linear_sched ? (int)blockIdx.x : xcd_chunk(blockIdx.x, gridDim.x));
+    const Tile tile = a.tiles[ti];
     if (HAS1D && tile.kind == 1) {
-        if constexpr (HAS1D) stage_tile<M, NU, WG, 1>(a, tile, smem);
+        if constexpr (HAS1D) stage_tile<M, NU, WG, 1>(a, ti, tile, smem);
     } else {
-        if constexpr (HAS2D) stage_tile<M, NU, TX, TY>(a, tile, smem);
+        if constexpr (HAS2D) stage_tile<M, NU, TX, TY>(a, ti, tile, smem);
     }
     if (a.stage == 3 && (a.cross ? a.xlast : owner_launch) && blockIdx.x == 0) {
         // t and the step counter are read by the next step's first stage only
         if (M != DETAILED) step_finish(a);
     }
+}
+
+// ------------------------------------------------------------------ halo source table
+// Workgroup t fills row t of the table: for each point of tile t that a sweep reads and
+// that is not its own block's cell, 8 * resolve() + its flags (bit 0 / 1: mirrored x / y
+// momentum, bit 2: a coarser level); 0 elsewhere (never read).
+template <int TX, int TY>
+__device__ void halo_table_tile(const StageArgs& a, int ti, const Tile& tile, int* row) {
+    using G = Geom<TX, TY>;
+    const DevBlock B = a.blk[tile.block];
+    CDom& D = cdom(a.dom, B.domain);
+    const int tw = min(TX, B.nx - tile.x0), th = min(TY, B.ny - tile.y0);
+    for (int p = threadIdx.x; p < G::NP; p += WG) {
+        int li, lj;
+        bool nx, ny;
+        point_needs<TX, TY>(p, tw, th, li, lj, nx, ny);
+        int v = 0;
+        const int bi = tile.x0 + li, bj = tile.y0 + lj;
+        if ((nx || ny) && !own_source(B, bi, bj)) {
+            unsigned fl = 0u;
+            const long long src = resolve(a, D, B.level, B.i0 + bi, B.j0 + bj, fl);
+            v = (int)(src * 8 + (long long)fl);
+        }
+        row[p] = v;
+    }
+}
+
+template <int TX, int TY>
+__global__ __launch_bounds__(WG) void halo_table_kernel(StageArgs a, int* out, int stride) {
+    const int ti = blockIdx.x;
+    const Tile tile = a.tiles[ti];
+    int* row = out + (size_t)ti * stride;
+    if (tile.kind == 1) halo_table_tile<WG, 1>(a, ti, tile, row);
+    else halo_table_tile<TX, TY>(a, ti, tile, row);
 }
 
 // ------------------------------------------------------------------ per-cell kernels
@@ -530,7 +584,8 @@ __device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, dou
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
         // pivot row: the first row at or below c with the largest |entry| in column c;
-        // rows are exchanged by selects so that the matrix stays in registers
+        // rows are exchanged by selects so that the matrix stays in registers, and only
+        // in wavefronts where some cell needs an exchange
         int p = c;
         double amax = fabs(J[c][c]);
 #pragma unroll
@@ -538,18 +593,20 @@ __device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, dou
             const double ar = fabs(J[r][c]);
             if (ar > amax) { amax = ar; p = r; }
         }
+        if (__any(p != c)) {
 #pragma unroll
-        for (int r = c + 1; r < NT; ++r) {
-            const bool sw = (r == p);
+            for (int r = c + 1; r < NT; ++r) {
+                const bool sw = (r == p);
 #pragma unroll
-            for (int q = c; q < NT; ++q) {
-                const double top = J[c][q], row = J[r][q];
-                J[c][q] = sw ? row : top;
-                J[r][q] = sw ? top : row;
+                for (int q = c; q < NT; ++q) {
+                    const double top = J[c][q], row = J[r][q];
+                    J[c][q] = sw ? row : top;
+                    J[r][q] = sw ? top : row;
+                }
+                const double wt = w[c], wr = w[r];
+                w[c] = sw ? wr : wt;
+                w[r] = sw ? wt : wr;
             }
-            const double wt = w[c], wr = w[r];
-            w[c] = sw ? wr : wt;
-            w[r] = sw ? wt : wr;
         }
         const double piv = J[c][c];
         if (!(fabs(piv) > 0.0) || !isfinite(piv)) st |= STB_NONFINITE;

@@ -73,6 +73,24 @@ hipError_t launch_stage(int model, int ns, int kind_mask, int tile_w, const Stag
     return o ? o->stage(kind_mask, tile_w, a, first_tile, ntiles, owner, s) : hipErrorInvalidValue;
 }
 
+int halo_table_stride(int tile_w, int kind_mask) {
+    int np2 = Geom<16, 16>::NP;
+    if (tile_w == 32) np2 = Geom<32, 8>::NP;
+    else if (tile_w == 64) np2 = Geom<64, 4>::NP;
+    const int np1 = Geom<WG, 1>::NP;
+    int n = (kind_mask & 1) ? np2 : 0;
+    if (kind_mask & 2) n = max(n, np1);
+    return n > 0 ? n : np2;
+}
+
+hipError_t launch_halo_table(int tile_w, const StageArgs& a, int* out, int stride, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    if (tile_w == 32) halo_table_kernel<32, 8><<<a.ntiles, WG, 0, s>>>(a, out, stride);
+    else if (tile_w == 64) halo_table_kernel<64, 4><<<a.ntiles, WG, 0, s>>>(a, out, stride);
+    else halo_table_kernel<16, 16><<<a.ntiles, WG, 0, s>>>(a, out, stride);
+    return hipGetLastError();
+}
+
 hipError_t launch_init(int model, int ns, int tile_w, const StageArgs& a, hipStream_t s) {
     (void)tile_w;
     const int n = a.ntiles;

@@ -84,3 +84,24 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(L.LibraryMissing):
         L.lib()
+
+
+def test_plan_flags_match_header(tmp_path):
+    """The binding's PLAN_* constants equal the header's JANC_PLAN_* values."""
+    import shutil
+    import subprocess
+    import paper_2504_13750_amd as janc
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    names = [n for n in dir(janc) if n.startswith("PLAN_")]
+    assert "PLAN_RESOLVE_HALOS" in names
+    lines = ["#include <stdio.h>", '#include "janc.h"', "int main(void) {"]
+    lines += [f'printf("{n} %d\\n", (int)JANC_{n});' for n in names]
+    lines += ["return 0; }"]
+    src = tmp_path / "flags.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "flags"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {ln.split()[0]: int(ln.split()[1]) for ln in out.splitlines()}
+    assert got == {n: getattr(janc, n) for n in names}

@@ -95,7 +95,10 @@ def test_autotune_chooses_a_candidate_and_keeps_results():
     choice, ms = plan.autotune(janc.time_of(bc), U, T, reps=3)
     print(f"  choice {choice}, ms {ms}", flush=True)
     assert choice in janc.AUTOTUNE_CANDIDATES
-    assert sorted(ms) == sorted(janc.AUTOTUNE_CANDIDATES) and min(ms.values()) == ms[choice]
+    assert sorted(ms) == sorted(janc.AUTOTUNE_CANDIDATES)
+    # a linear-order candidate is charged 3 % on its time (it reads more HBM bytes)
+    charged = {k: v * (1.03 if k[1] else 1.0) for k, v in ms.items()}
+    assert min(charged.values()) == charged[choice]
     assert torch.equal(U, U_before) and torch.equal(T, T_before)   # the state is only read
     t = torch.zeros(1, dtype=torch.float64, device=U.device)
     ctx.step_blocks(plan, janc.time_of(bc), U, T, 3, t)
@@ -123,6 +126,22 @@ def test_linear_schedule_agrees_bitwise():
     assert np.array_equal(U.cpu().numpy(), Ua) and np.array_equal(t.cpu().numpy(), ta)
     plan.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("which", ["small", "small-9sp", "amr-637-blocks"])
+def test_halo_table_equals_resolved_sources_bitwise(which):
+    """Stage launches that read off-block and ring sources from the plan's halo source
+    table (the default) against launches that resolve them in the kernel
+    (PLAN_RESOLVE_HALOS), bitwise: synchronous and crossover advance, every tile width on
+    the small hierarchies."""
+    from cases import amr_case
+    bc = {"small": _small_amr, "small-9sp": _small_detailed_amr, "amr-637-blocks": amr_case}[which]()
+    tiles = [16, 32, 64] if which != "amr-637-blocks" else [0]
+    for cross in (0, janc.PLAN_CROSSOVER):
+        for tile in tiles:
+            Ua, Ta, ta = run_blocks(bc, 2, flags=cross, tile=tile)
+            Ub, Tb, tb = run_blocks(bc, 2, flags=cross | janc.PLAN_RESOLVE_HALOS, tile=tile)
+            assert np.array_equal(Ua, Ub) and np.array_equal(Ta, Tb) and np.array_equal(ta, tb)
 
 
 @pytest.mark.parametrize("tile", [16, 32, 64])
