@@ -259,8 +259,8 @@ def main():
         choice, cand_ms = plan.autotune(tm, U0, T0, reps=5)
         del U0, T0
         log(f"[bench] autotuner: tile width {choice[0]}, "
-            f"{'linear' if choice[1] else 'XCD-contiguous'} order; candidates (ms per "
-            f"first-stage launch) "
+            f"{'linear' if choice[1] else 'XCD-contiguous'} order; candidates (median ms per "
+            f"stage triple) "
             + ", ".join(f"{w}/{'lin' if l else 'xcd'} {v:.3f}" for (w, l), v in cand_ms.items()))
     else:
         choice, cand_ms = fixed, {}

@@ -233,17 +233,18 @@ janc_status janc_plan_set_tile(janc_plan *plan, int tile_width);
  * whose halos overlap, are read through the same L2. Results do not depend on either. */
 janc_status janc_plan_set_schedule(janc_plan *plan, int tile_width, int linear);
 
-/* Autotuner of the batched stage launch (systems pattern, not in the paper): times each
- * candidate -- 2-D tile width 16, 32, 64 (16x16, 32x8, 64x4 cells) times the two
- * workgroup orders of janc_plan_set_schedule; 1-D-only plans: the two orders -- over
- * `reps` (1..1000) first-stage launches on the state U, T (device, read only; only the
- * plan's workspaces are written), with HIP events on `stream`, and keeps the fastest in
- * the plan (synchronous on the host); a linear-order candidate's time is charged 3 %
- * extra, since that order reads 2-3x the HBM bytes and ties between the orders are
- * timing noise. choice (host [2], may be NULL) receives the tile
- * width and the order; ms (host [6], may be NULL) the median launch time of each
- * candidate in the order (16, XCD), (16, linear), (32, XCD), (32, linear), (64, XCD),
- * (64, linear), -1 where not timed. Every candidate gives bitwise the same results. */
+/* Autotuner of the batched stage launch (systems pattern, not in the paper). Candidates:
+ * 2-D tile width 16, 32, 64 (16x16, 32x8, 64x4 cells) times the two workgroup orders of
+ * janc_plan_set_schedule; 1-D-only plans: the two orders. A measurement is one RK stage
+ * triple on the state U, T (device, read only; only the plan's workspaces are written),
+ * timed with HIP events on `stream`; the candidates are measured in `reps` (1..1000)
+ * interleaved rounds after one warm-up round and compared by their median. The plan keeps
+ * its current shape unless a candidate is faster by more than 2 %; a linear-order
+ * candidate's time is charged 3 % extra, since that order reads 2-3x the HBM bytes.
+ * Synchronous on the host. choice (host [2], may be NULL) receives the tile width and the
+ * order kept; ms (host [6], may be NULL) the median triple time of each candidate in the
+ * order (16, XCD), (16, linear), (32, XCD), (32, linear), (64, XCD), (64, linear), -1
+ * where not timed. Every candidate gives bitwise the same results. */
 janc_status janc_plan_autotune(janc_ctx *ctx, janc_plan *plan, const janc_time *time,
                                const double *U, const double *T, int reps, int *choice,
                                double *ms, void *stream);

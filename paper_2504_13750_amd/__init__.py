@@ -167,7 +167,8 @@ class Plan:
         self.ctx._check(L.lib().janc_plan_set_schedule(self.h, int(width), int(linear)))
 
     def autotune(self, time, U, T, reps=5, stream=None):
-        """janc_plan_autotune: returns ((tile width, linear order), {candidate: ms})."""
+        """janc_plan_autotune: returns ((tile width, linear order) kept, {candidate: median
+        ms of one RK stage triple})."""
         choice = (C.c_int * 2)()
         ms = (C.c_double * 6)()
         self.ctx._check(L.lib().janc_plan_autotune(

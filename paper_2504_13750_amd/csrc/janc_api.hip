@@ -788,17 +788,20 @@ void drop_graph(janc_plan* P) {
     P->have_graph = false;
 }
 
-// Autotuner of the stage launch: each candidate (2-D tile width 16, 32 or 64 --
-// 16 x 16, 32 x 8, 64 x 4 cells -- and the tile order of the workgroups) is timed
-// with HIP events over `reps` first-stage launches of the plan on the state (U, T);
-// the fastest is kept in the plan. The linear order reads 2 to 3 times the HBM bytes
-// of the XCD-contiguous order (halo rows shared by neighbouring tiles are fetched
-// once per XCD L2 instead of once per tile); on an ALU-bound launch the two times
-// differ by noise, so a linear-order candidate is charged LINEAR_HANDICAP on its time
-// and wins only when it is clearly faster. Only the plan's own workspaces are written
-// (the first stage's output goes to the stage buffer), and every candidate computes
-// the same result bitwise, so the choice changes speed only.
+// Autotuner of the stage launch. Candidates: the 2-D tile width 16, 32 or 64 (16 x 16,
+// 32 x 8, 64 x 4 cells) times the order in which workgroups take tiles. A measurement
+// is one RK stage triple of the plan on the state (U, T), timed with HIP events: stage
+// 1 reads U and T, stages 2 and 3 the plan's stage buffers and U as U^(0), and every
+// output goes to the plan's workspaces (the caller's arrays are only read). The
+// candidates are measured in `reps` interleaved rounds, so that a clock ramp or a noisy
+// interval falls on all of them, and compared by their median. The plan keeps its
+// current shape unless a candidate is faster by more than KEEP_MARGIN. The linear order
+// reads 2 to 3 times the HBM bytes of the XCD-contiguous order (halo rows shared by
+// neighbouring tiles are fetched once per XCD L2 instead of once per tile), so a
+// linear-order candidate is charged LINEAR_HANDICAP on its time. Every candidate
+// computes the same result bitwise: the choice changes speed only.
 constexpr double LINEAR_HANDICAP = 1.03;
+constexpr double KEEP_MARGIN = 0.02;
 
 janc_status autotune(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U, double* T, int reps,
                      double* ms_out, hipStream_t s) {
@@ -806,77 +809,94 @@ janc_status autotune(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U, 
     struct Cand { int w, lin; };
     std::vector<Cand> cands;
     const int widths[3] = {16, 32, 64};
+    const bool twod = (P->kind_mask & 1) != 0;   // 1-D tiles only: the width does not apply
     for (int wi = 0; wi < 3; ++wi) {
-        if (!(P->kind_mask & 1) && wi > 0) break;   // 1-D tiles only: the width does not apply
+        if (!twod && wi > 0) break;
         for (int lin = 0; lin < 2; ++lin) cands.push_back({widths[wi], lin});
     }
     const int w0 = P->tile_w, l0 = P->linear_sched;
+    int inc = -1;   // the plan's current shape among the candidates
+    for (size_t k = 0; k < cands.size(); ++k)
+        if (cands[k].lin == l0 && (!twod || cands[k].w == w0)) inc = (int)k;
     hipEvent_t ev[2];
+    double* tbuf = nullptr;   // t of the stage triples (advanced by the one-step models' stage 3)
     HIPCHK(c, hipEventCreate(&ev[0]), "hipEventCreate");
     if (hipEventCreate(&ev[1]) != hipSuccess) {
         hipEventDestroy(ev[0]);
         return fail(c, JANC_EHIP, "hipEventCreate");
     }
-    double best = INFINITY;
-    int bw = w0, bl = l0;
-    hipError_t e = hipSuccess;
+    hipError_t e = hipMalloc((void**)&tbuf, sizeof(double) * (size_t)std::max(P->ndom, 1));
+    if (e == hipSuccess) e = hipMemsetAsync(tbuf, 0, sizeof(double) * (size_t)std::max(P->ndom, 1), s);
     janc_status st = JANC_OK;
-    for (size_t k = 0; k < cands.size() && e == hipSuccess && !st; ++k) {
-        if (cands[k].w != P->tile_w) {
-            P->tile_w = cands[k].w;
-            st = build_tiles(c, P);
-            if (st) break;
-        }
-        P->linear_sched = cands[k].lin;
-        StageArgs base = base_args(P, tm, U, T, nullptr, nullptr, 0);
-        base.cross = 0;   // timed as one synchronous launch over every tile
-        base.red = Reduce{P->dred, P->red_stride, P->nunits, P->ndom, 0};
-        base.strang = 0;
-        base.tm.t_end = 0.0;   // no clipping: t is not read
-        StageArgs a0 = base;
-        a0.Uin = U;
-        a0.Tin = T;
-        a0.Tout = P->T1;   // the entry T solve writes the workspace, not the caller's T
-        e = launch_zero_int(P->dstep, s);
-        if (e == hipSuccess) e = launch_clear_reduce(base.red, -1, s);
-        if (e == hipSuccess) e = launch_init(c->model, c->ns, P->tile_w, a0, s);
-        StageArgs a = base;
-        a.stage = 1;
-        a.Uin = U;
-        a.Tin = P->T1;
-        a.Uout = P->U1;
-        a.Tout = P->T2;
-        a.reduce_out = 1;
-        std::vector<float> times;
-        for (int r = 0; r <= reps && e == hipSuccess; ++r) {   // r = 0: warm-up
-            e = hipEventRecord(ev[0], s);
-            if (e == hipSuccess) e = launch_stage(c->model, c->ns, P->kind_mask, P->tile_w, a, 0, a.ntiles, s);
+    std::vector<std::vector<float>> times(cands.size());
+    for (int r = 0; r <= reps && e == hipSuccess && !st; ++r) {   // round 0: warm-up
+        for (size_t k = 0; k < cands.size() && e == hipSuccess && !st; ++k) {
+            if (cands[k].w != P->tile_w) {
+                P->tile_w = cands[k].w;
+                st = build_tiles(c, P);
+                if (st) break;
+            }
+            P->linear_sched = cands[k].lin;
+            StageArgs base = base_args(P, tm, U, T, tbuf, nullptr, 0);
+            base.cross = 0;   // timed as synchronous launches over every tile
+            base.red = Reduce{P->dred, P->red_stride, P->nunits, P->ndom, 0};
+            base.strang = 0;
+            base.tm.t_end = 0.0;   // no clipping: t is not read
+            StageArgs a0 = base;
+            a0.Uin = U;
+            a0.Tin = T;
+            a0.Tout = P->T1;   // the entry T solve writes the workspace, not the caller's T
+            e = launch_zero_int(P->dstep, s);
+            if (e == hipSuccess) e = launch_clear_reduce(base.red, -1, s);
+            if (e == hipSuccess) e = launch_init(c->model, c->ns, P->tile_w, a0, s);
+            double* Uin[3] = {U, P->U1, P->U2};
+            double* Uout[3] = {P->U1, P->U2, P->U1};
+            double* Tin[3] = {P->T1, P->T2, P->T1};
+            double* Tout[3] = {P->T2, P->T1, P->T2};
+            if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+            for (int sg = 1; sg <= 3 && e == hipSuccess; ++sg) {
+                StageArgs a = base;
+                a.stage = sg;
+                a.Uin = Uin[sg - 1];
+                a.Uout = Uout[sg - 1];
+                a.Tin = Tin[sg - 1];
+                a.Tout = Tout[sg - 1];
+                a.reduce_out = (sg == 3 && c->model == DETAILED) ? 0 : 1;
+                e = launch_stage(c->model, c->ns, P->kind_mask, P->tile_w, a, 0, a.ntiles, s);
+            }
             if (e == hipSuccess) e = hipEventRecord(ev[1], s);
             if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
             float f = 0.0f;
             if (e == hipSuccess) e = hipEventElapsedTime(&f, ev[0], ev[1]);
-            if (r > 0) times.push_back(f);
-        }
-        if (e != hipSuccess) break;
-        std::sort(times.begin(), times.end());
-        const double med = times.empty() ? INFINITY : times[times.size() / 2];
-        if (ms_out) ms_out[k] = med;
-        const double charged = cands[k].lin ? med * LINEAR_HANDICAP : med;
-        if (charged < best) {
-            best = charged;
-            bw = cands[k].w;
-            bl = cands[k].lin;
+            if (e == hipSuccess && r > 0) times[k].push_back(f);
         }
     }
     hipEventDestroy(ev[0]);
     hipEventDestroy(ev[1]);
+    if (tbuf) {
+        hipStreamSynchronize(s);
+        hipFree(tbuf);
+    }
+    int bw = w0, bl = l0;
+    if (e == hipSuccess && !st) {
+        std::vector<double> med(cands.size(), INFINITY);
+        for (size_t k = 0; k < cands.size(); ++k) {
+            std::sort(times[k].begin(), times[k].end());
+            if (!times[k].empty()) med[k] = times[k][times[k].size() / 2];
+            if (ms_out) ms_out[k] = med[k];
+        }
+        auto charged = [&](size_t k) { return cands[k].lin ? med[k] * LINEAR_HANDICAP : med[k]; };
+        double best = (inc >= 0) ? charged((size_t)inc) * (1.0 - KEEP_MARGIN) : INFINITY;
+        for (size_t k = 0; k < cands.size(); ++k) {
+            if (charged(k) < best) {
+                best = charged(k);
+                bw = cands[k].w;
+                bl = cands[k].lin;
+            }
+        }
+    }
     if (ms_out)
         for (size_t k = cands.size(); k < 6; ++k) ms_out[k] = -1.0;
-    // keep the fastest (or restore the previous choice after a failure)
-    if (e != hipSuccess || st) {
-        bw = w0;
-        bl = l0;
-    }
     P->linear_sched = bl;
     if (P->tile_w != bw) {
         P->tile_w = bw;

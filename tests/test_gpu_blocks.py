@@ -81,8 +81,8 @@ def test_per_level_launches_equal_batched_bitwise():
 
 def test_autotune_chooses_a_candidate_and_keeps_results():
     """janc_plan_autotune times the six (tile width, workgroup order) candidates on the
-    state and keeps the fastest; stepping with the tuned plan (and with JANC_PLAN_AUTOTUNE,
-    and with the linear order set by hand) gives the default plan's result bitwise."""
+    state and keeps the default shape unless a candidate is clearly faster; stepping with
+    the tuned plan (and with JANC_PLAN_AUTOTUNE) gives the default plan's result bitwise."""
     import torch
     from gpu_util import init_blocks, context_for
     bc = _small_detailed_amr()
@@ -95,10 +95,15 @@ def test_autotune_chooses_a_candidate_and_keeps_results():
     choice, ms = plan.autotune(janc.time_of(bc), U, T, reps=3)
     print(f"  choice {choice}, ms {ms}", flush=True)
     assert choice in janc.AUTOTUNE_CANDIDATES
-    assert sorted(ms) == sorted(janc.AUTOTUNE_CANDIDATES)
-    # a linear-order candidate is charged 3 % on its time (it reads more HBM bytes)
+    assert sorted(ms) == sorted(janc.AUTOTUNE_CANDIDATES) and all(v > 0 for v in ms.values())
+    # a linear-order candidate is charged 3 % on its time (it reads more HBM bytes); the
+    # default shape (16, XCD order) is kept unless a candidate beats it by more than 2 %
     charged = {k: v * (1.03 if k[1] else 1.0) for k, v in ms.items()}
-    assert min(charged.values()) == charged[choice]
+    best = min(charged, key=charged.get)
+    if charged[best] < 0.98 * charged[(16, 0)]:
+        assert choice == best
+    else:
+        assert choice == (16, 0)
     assert torch.equal(U, U_before) and torch.equal(T, T_before)   # the state is only read
     t = torch.zeros(1, dtype=torch.float64, device=U.device)
     ctx.step_blocks(plan, janc.time_of(bc), U, T, 3, t)
