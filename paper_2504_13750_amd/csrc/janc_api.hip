@@ -517,7 +517,7 @@ janc_status build_plan(janc_ctx* c, int nd, const janc_domain* doms, int nb, con
     if ((st = pupload(P.get(), &P->dring, P->ring_blocks))) return st;
     P->red_stride = 2 * P->nunits + nd;
     const int ntrip = (flags & JANC_PLAN_CROSSOVER) ? P->maxlev + 1 : 1;   // slot sets
-    if ((st = palloc(P.get(), &P->dred, (size_t)RED_BUFS * ntrip * P->red_stride))) return st;
+    if ((st = palloc(P.get(), &P->dred, (size_t)RED_BUFS * ntrip * P->red_stride * SLOT_WORDS))) return st;
     if ((st = palloc(P.get(), &P->ddt, nd))) return st;
     if ((st = palloc(P.get(), &P->dstep, 1))) return st;
     if ((st = palloc(P.get(), &P->U1, (size_t)nU * pool))) return st;
@@ -631,7 +631,7 @@ StageArgs base_args(janc_plan* P, const janc_time* tm, double* U, double* T, dou
 // Level l's slot set in the crossover advance.
 Reduce level_red(const janc_plan* P, const StageArgs& base, int l) {
     Reduce r = base.red;
-    if (base.cross) r.buf = P->dred + (size_t)l * RED_BUFS * P->red_stride;
+    if (base.cross) r.buf = P->dred + (size_t)l * RED_BUFS * P->red_stride * SLOT_WORDS;
     return r;
 }
 

@@ -21,13 +21,18 @@ __device__ __forceinline__ CDom& cdom(const DevDomain* p, int d) { return ((CDom
 // ------------------------------------------------------------------ small helpers
 __device__ __forceinline__ double sq(double x) { return x * x; }
 
+// Word of slot idx of buffer buf (each slot alone in a 128-byte line).
+__device__ __forceinline__ size_t slot_word(int stride, int buf, int idx) {
+    return ((size_t)buf * stride + idx) * SLOT_WORDS;
+}
+
 __device__ __forceinline__ double slot_get(const Reduce& r, int buf, int idx) {
-    return __longlong_as_double((long long)r.buf[(size_t)buf * r.stride + idx]);
+    return __longlong_as_double((long long)r.buf[slot_word(r.stride, buf, idx)]);
 }
 
 __device__ __forceinline__ void slot_max(const Reduce& r, int buf, int idx, double v) {
     // v >= 0: the bit pattern orders like the value
-    atomicMax(&r.buf[(size_t)buf * r.stride + idx], (unsigned long long)__double_as_longlong(v));
+    atomicMax(&r.buf[slot_word(r.stride, buf, idx)], (unsigned long long)__double_as_longlong(v));
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -304,8 +309,8 @@ __device__ __forceinline__ double step_dt(const StageArgs& a, int d, int bin) {
     } else if (a.cross) {
         double m = 0.0;
         for (int l = 0; l < a.xlevels; ++l)
-            m = fmax(m, __longlong_as_double((long long)a.xred[((size_t)l * RED_BUFS + bin) * a.red.stride +
-                                                               2 * a.red.nunits + d]));
+            m = fmax(m, __longlong_as_double((long long)a.xred[slot_word(a.red.stride, l * RED_BUFS + bin,
+                                                                         2 * a.red.nunits + d)]));
         dt = a.tm.cfl / m;
     } else {
         dt = a.tm.cfl / slot_get(a.red, bin, 2 * a.red.nunits + d);
@@ -360,7 +365,7 @@ __device__ void record_dt(const StageArgs& a) {
 __device__ void stage_bookkeeping(const StageArgs& a, int owner_launch) {
     const int s = a.stage;
     const int bclear = (s + 1) % 3;
-    for (int q = threadIdx.x; q < a.red.stride; q += WG) a.red.buf[(size_t)bclear * a.red.stride + q] = 0ull;
+    for (int q = threadIdx.x; q < a.red.stride; q += WG) a.red.buf[slot_word(a.red.stride, bclear, q)] = 0ull;
     if (a.cross) owner_launch = a.xfirst;
     if (!owner_launch) return;
     if (s == 1 && !a.strang) record_dt(a);   // under Strang splitting the first chemistry launch does

@@ -660,7 +660,7 @@ __global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
         }
     }
     if (phase == 2)   // buffer 3 was read by stage 1; clean for the next step's first half
-        for (int q = threadIdx.x; q < a.red.stride; q += WG) a.red.buf[(size_t)3 * a.red.stride + q] = 0ull;
+        for (int q = threadIdx.x; q < a.red.stride; q += WG) a.red.buf[slot_word(a.red.stride, 3, q)] = 0ull;
     if (!(dt > 0.0)) return;
     double sx = 0.0, sy = 0.0, sc = 0.0;
     unsigned st = 0u;

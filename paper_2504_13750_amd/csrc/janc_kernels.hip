@@ -56,8 +56,8 @@ hipError_t launch_zero_int(int* p, hipStream_t s) {
 }
 
 hipError_t launch_clear_reduce(const Reduce& r, int which, hipStream_t s) {
-    const int n = (which < 0) ? RED_BUFS * r.stride : r.stride;
-    unsigned long long* p = (which < 0) ? r.buf : r.buf + (size_t)which * r.stride;
+    const int n = ((which < 0) ? RED_BUFS * r.stride : r.stride) * SLOT_WORDS;
+    unsigned long long* p = (which < 0) ? r.buf : r.buf + (size_t)which * r.stride * SLOT_WORDS;
     clear_kernel<<<1, WG, 0, s>>>(p, n);
     return hipGetLastError();
 }
