@@ -656,29 +656,60 @@ constexpr int MAXT = 2 + MAXP;
 
 template <int M, int NU>
 __global__ __launch_bounds__(AWG) void adj_finish(AdjArgs A) {
-    __shared__ double sh[8];
+    __shared__ double sh[4][AWG / 64];
     __shared__ double red[4];
     __shared__ double dlam[MAXT][NU], dacc[MAXT][NU], dth[MAXT];
     __shared__ long long tc[MAXT];
     __shared__ int uselam[MAXT];
     const AdjGrid& g = A.g;
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int q = threadIdx.x; q < A.nbd; q += AWG) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s4[k] += A.part[(size_t)q * 4 + k];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const double t = block_sum(s4[k], sh);
-        if (threadIdx.x == 0) red[k] = t;
-    }
-    __syncthreads();
     const int nal = g.twod ? 2 : 1;
     const int nsd = A.seedU ? A.np : 0;
     const int T = nal + nsd;
     const int k = threadIdx.x;
+    // The state at the cell of this thread's task (an alpha term at its argmax cell, or a
+    // probe's loss seed) does not depend on the block partials: it is loaded first, so
+    // that its latency overlaps the reduction.
+    long long cell = -1;
+    double Vc[NU];
+    double Tc = 0.0;
+#pragma unroll
+    for (int f = 0; f < NU; ++f) Vc[f] = 0.0;
     if (k < T) {
-        long long cell = -1;
+        if (k < nal) {
+            const long long ca = A.argm[k];
+            if (ca >= 0 && ca < A.n) cell = ca;   // (no cell attains the maximum only for non-finite data)
+        } else {
+            cell = A.pc[k - nal];
+        }
+        if (cell >= 0) {
+            const double* src = (k < nal) ? A.V : A.seedU;
+#pragma unroll
+            for (int f = 0; f < NU; ++f) Vc[f] = src[(size_t)f * A.n + cell];
+            if (M == DETAILED) Tc = (k < nal) ? A.VT[cell] : A.seedT[cell];
+        }
+    }
+    // the four sums of the block partials in one pass: per wavefront by shuffles, then
+    // the wavefronts' sums in order
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = threadIdx.x; q < A.nbd; q += AWG) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s4[j] += A.part[(size_t)q * 4 + j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s4[j] += __shfl_xor(s4[j], o, 64);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sh[j][threadIdx.x >> 6] = s4[j];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int q = 0; q < AWG / 64; ++q) t += sh[threadIdx.x][q];
+        red[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (k < T) {
         double dl[NU], da[NU], th = 0.0;
         int ul = 0;
 #pragma unroll
@@ -686,15 +717,9 @@ __global__ __launch_bounds__(AWG) void adj_finish(AdjArgs A) {
         if (k < nal) {
             const int d = k;
             const double mua = red[d];
-            const long long ca = A.argm[d];
-            if (ca >= 0 && ca < A.n) {   // (no cell attains the maximum only for non-finite data)
-                cell = ca;
-                double Vc[NU];
-#pragma unroll
-                for (int f = 0; f < NU; ++f) Vc[f] = A.V[(size_t)f * A.n + ca];
-                const double Tca = (M == DETAILED) ? A.VT[ca] : 0.0;
+            if (cell >= 0) {
                 PState<NU> P;
-                pstate<M, NU, true>(g, cmech(A.mech), Vc, Tca, P);
+                pstate<M, NU, true>(g, cmech(A.mech), Vc, Tc, P);
                 const double rho = Vc[0];
                 const double w = d == 0 ? P.u : P.v;
                 const double sg = (w > 0.0) ? 1.0 : ((w < 0.0) ? -1.0 : 0.0);
@@ -717,12 +742,8 @@ __global__ __launch_bounds__(AWG) void adj_finish(AdjArgs A) {
         } else {
             // loss seed of the step start state: acc += dt w_q dp/dU at probe q
             const int q = k - nal;
-            cell = A.pc[q];
-            double Vc[NU];
-#pragma unroll
-            for (int f = 0; f < NU; ++f) Vc[f] = A.seedU[(size_t)f * A.n + cell];
             PState<NU> P;
-            pstate<M, NU, false>(g, cmech(A.mech), Vc, (M == DETAILED) ? A.seedT[cell] : 0.0, P);
+            pstate<M, NU, false>(g, cmech(A.mech), Vc, Tc, P);
             const double s = A.dt * A.pw[q];
 #pragma unroll
             for (int f = 0; f < NU; ++f) da[f] = s * P.dp[f];
