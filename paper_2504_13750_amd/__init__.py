@@ -39,6 +39,7 @@ BC_PERIODIC, BC_ZEROGRAD, BC_SLIPWALL, BC_DIRICHLET = 0, 1, 2, 3
 PLAN_DEFAULT, PLAN_PER_BLOCK, PLAN_NO_GRAPH, PLAN_CROSSOVER, PLAN_PER_LEVEL = 0, 1, 2, 4, 8
 PLAN_AUTOTUNE = 16
 PLAN_RESOLVE_HALOS = 32
+CHEM_GENERIC, CHEM_SPECIALIZED = 0, 1
 AUTOTUNE_CANDIDATES = [(16, 0), (16, 1), (32, 0), (32, 1), (64, 0), (64, 1)]
 SPLIT_LIE, SPLIT_STRANG = 0, 1
 JAC_FROZEN_T, JAC_FULL = 0, 1
@@ -196,6 +197,15 @@ class Plan:
             pass
 
 
+def chem_kernel_check(mech):
+    """janc_chem_kernel_check: generate and compile (hipRTC, no device) the chemistry
+    kernel specialised to `mech`; returns (status, compiler log)."""
+    m = _Mech(mech)
+    buf = C.create_string_buffer(1 << 16)
+    st = L.lib().janc_chem_kernel_check(C.byref(m.s), buf, len(buf))
+    return int(st), buf.value.decode(errors="replace")
+
+
 class Context:
     """A library context (janc_create) on one HIP device for one model."""
 
@@ -214,6 +224,17 @@ class Context:
     @property
     def nfields(self):
         return int(L.lib().janc_num_fields(self.h))
+
+    @property
+    def chem_kernel(self):
+        """janc_get_chem_kernel: CHEM_GENERIC or CHEM_SPECIALIZED."""
+        mode = C.c_int()
+        self._check(L.lib().janc_get_chem_kernel(self.h, C.byref(mode)))
+        return mode.value
+
+    @chem_kernel.setter
+    def chem_kernel(self, mode):
+        self._check(L.lib().janc_set_chem_kernel(self.h, int(mode)))
 
     def _check(self, st):
         if st != 0:

@@ -56,6 +56,9 @@ EXPORTS = {
     "janc_destroy": (None, [VP]),
     "janc_last_error": (C.c_char_p, [VP]),
     "janc_num_fields": (I, [VP]),
+    "janc_set_chem_kernel": (I, [VP, I]),
+    "janc_get_chem_kernel": (I, [VP, PI]),
+    "janc_chem_kernel_check": (I, [C.POINTER(janc_mech), C.c_char_p, I]),
     "janc_sync_status": (I, [VP, VP]),
     "janc_init_state": (I, [VP, C.POINTER(janc_physics), C.c_longlong, VP, VP, VP, VP]),
     "janc_step": (I, [VP, C.POINTER(janc_grid), C.POINTER(janc_physics), C.POINTER(janc_time),

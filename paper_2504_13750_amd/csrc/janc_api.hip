@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/janc.h"
+#include "janc_rtc.h"
 #include "janc_internal.h"
 
 using namespace janc;
@@ -51,6 +52,11 @@ struct janc_ctx {
     size_t adj_doubles = 0;
     hipStream_t adj_stream = nullptr;   // auxiliary stream of the adjoint's recompute
     hipEvent_t adj_ev[5] = {};
+    // chemistry kernel specialised to the mechanism's structure (detailed model)
+    hipModule_t chem_mod = nullptr;
+    hipFunction_t chem_fn = nullptr;
+    int chem_mode = JANC_CHEM_GENERIC;
+    std::string chem_log;               // why no specialised kernel could be built
 };
 
 struct GraphKey {
@@ -58,10 +64,11 @@ struct GraphKey {
     int cap;
     double cfl, dt_fixed, t_end;
     int split, jac;
+    int chem;   // the context's chemistry kernel (generic or specialised)
     bool operator==(const GraphKey& o) const {
         return U == o.U && T == o.T && t == o.t && dt_log == o.dt_log && cap == o.cap &&
                cfl == o.cfl && dt_fixed == o.dt_fixed && t_end == o.t_end && split == o.split &&
-               jac == o.jac;
+               jac == o.jac && chem == o.chem;
     }
 };
 
@@ -216,6 +223,7 @@ template <class T> janc_status pupload(janc_plan* P, T** p, const std::vector<T>
 }
 
 // --------------------------------------------------------------- mechanism
+// The mechanism in the layout the kernels read (host copy; validated).
 janc_status build_mech(janc_ctx* c, const janc_mech* m) {
     if (!m || m->ns < 2 || m->ns > MAXS || m->nr < 0 || m->nr > MAXR)
         return fail(c, JANC_EINVAL, "mechanism sizes out of range (ns 2..%d, nr 0..%d)", MAXS, MAXR);
@@ -269,9 +277,14 @@ janc_status build_mech(janc_ctx* c, const janc_mech* m) {
         }
         d.dnsum[i] = ds;
     }
+    return JANC_OK;
+}
+
+// The mechanism tables on the device.
+janc_status upload_mech(janc_ctx* c) {
     janc_status st = dalloc(c, &c->dmech, 1);
     if (st) return st;
-    HIPCHK(c, hipMemcpy(c->dmech, &d, sizeof(d), hipMemcpyHostToDevice), "hipMemcpy mech");
+    HIPCHK(c, hipMemcpy(c->dmech, &c->hmech, sizeof(c->hmech), hipMemcpyHostToDevice), "hipMemcpy mech");
     return JANC_OK;
 }
 
@@ -635,6 +648,18 @@ Reduce level_red(const janc_plan* P, const StageArgs& base, int l) {
     return r;
 }
 
+// The chemistry launch of context c: the kernel specialised to the mechanism's structure
+// when it is built and selected (not for the species + T Jacobian), else the generic one.
+hipError_t chem_launch(janc_ctx* c, const StageArgs& a, hipStream_t s) {
+    if (c->model != DETAILED || a.ntiles <= 0) return hipSuccess;
+    if (c->chem_mode == JANC_CHEM_SPECIALIZED && c->chem_fn && !a.full_jac) {
+        StageArgs arg = a;
+        void* params[] = {&arg};
+        return hipModuleLaunchKernel(c->chem_fn, (unsigned)a.ntiles, 1, 1, WG, 1, 1, 0, s, params, nullptr);
+    }
+    return launch_chem(c->model, c->ns, 0, a, s);
+}
+
 // The first half chemistry launch of a Strang-split step (in place on U, T).
 hipError_t launch_chem_first_half(janc_plan* P, const StageArgs& base, const Reduce& red, double* U,
                                   double* T, int first_tile, int ntiles, int xfirst, hipStream_t s) {
@@ -649,7 +674,7 @@ hipError_t launch_chem_first_half(janc_plan* P, const StageArgs& base, const Red
     a.ntiles = ntiles;
     a.chem_phase = 1;
     a.xfirst = xfirst;
-    return launch_chem(P->ctx->model, P->ctx->ns, P->tile_w, a, s);
+    return chem_launch(P->ctx, a, s);
 }
 
 // One crossover step (Fig. 2a, Alg. 2): two steps of level l + 1 before each step of
@@ -703,7 +728,7 @@ hipError_t enqueue_crossover(janc_plan* P, const StageArgs& base, double* U, dou
             a.xlast = (l == 0) ? 1 : 0;
             a.xskip_cov = last_of_level ? 1 : 0;
             a.chem_phase = base.strang ? 2 : 0;
-            e = launch_chem(model, ns, P->tile_w, a, s);
+            e = chem_launch(P->ctx, a, s);
         }
     };
     struct Rec {
@@ -769,7 +794,7 @@ hipError_t enqueue_step(janc_plan* P, const StageArgs& base, double* U, double* 
     a.Tin = T;
     a.Tout = T;
     a.chem_phase = base.strang ? 2 : 0;
-    if (e == hipSuccess && model == DETAILED) e = launch_chem(model, ns, P->tile_w, a, s);
+    if (e == hipSuccess && model == DETAILED) e = chem_launch(P->ctx, a, s);
     for (int l = P->maxlev; l >= 1 && e == hipSuccess; --l)
         e = launch_restrict(model, ns, a, P->dfine + P->fine_off[l], (int)P->fine[l].size(), s);
     if (e == hipSuccess && !P->ring_blocks.empty())
@@ -945,7 +970,7 @@ janc_status run_steps(janc_ctx* c, janc_plan* P, const janc_time* tm, double* U,
     }
     // the step count enters the captured launches only as the bound of dt_log
     const GraphKey key{U, T, t, dt_log, dt_log ? nsteps : 0, tm->cfl, tm->dt_fixed, tm->t_end,
-                       tm->split, tm->jac};
+                       tm->split, tm->jac, c->chem_mode};
     if (!P->have_graph || !(P->gkey == key)) {
         drop_graph(P);
         hipStream_t cs;
@@ -1245,7 +1270,7 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
         a.Tin = Tof(U);
         a.Tout = Tof(U);
         a.chem_phase = 0;
-        if (e == hipSuccess) e = launch_chem(model, ns, P->tile_w, a, q);
+        if (e == hipSuccess) e = chem_launch(P->ctx, a, q);
         return e;
     };
     // one full forward step: stage inputs into o1, o2, the chemistry input into x3
@@ -1601,8 +1626,21 @@ janc_status janc_create(janc_ctx** out, int model, const janc_mech* mech, int de
     c->model = model;
     if (model == DETAILED) {
         janc_status st = build_mech(c.get(), mech);
+        if (!st) st = upload_mech(c.get());
         if (st) return st;
         c->ns = mech->ns;
+        std::vector<char> code;
+        if (chem_spec_code(chem_spec_source(c->hmech), &code, &c->chem_log)) {
+            if (hipModuleLoadData(&c->chem_mod, code.data()) != hipSuccess ||
+                hipModuleGetFunction(&c->chem_fn, c->chem_mod, CHEM_SPEC_KERNEL) != hipSuccess) {
+                c->chem_log = "loading the specialised chemistry kernel failed";
+                if (c->chem_mod) hipModuleUnload(c->chem_mod);
+                c->chem_mod = nullptr;
+                c->chem_fn = nullptr;
+            } else {
+                c->chem_mode = JANC_CHEM_SPECIALIZED;
+            }
+        }
     }
     c->nU = n_fields(model, c->ns);
     {
@@ -1626,12 +1664,45 @@ void janc_destroy(janc_ctx* c) {
     for (hipEvent_t e : c->adj_ev)
         if (e) hipEventDestroy(e);
     if (c->adj_stream) hipStreamDestroy(c->adj_stream);
+    if (c->chem_mod) hipModuleUnload(c->chem_mod);
     delete c;
 }
 
 const char* janc_last_error(const janc_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 int janc_num_fields(const janc_ctx* c) { return c ? c->nU : 0; }
+
+janc_status janc_set_chem_kernel(janc_ctx* c, int mode) {
+    if (!c) return JANC_EINVAL;
+    if (mode != JANC_CHEM_GENERIC && mode != JANC_CHEM_SPECIALIZED)
+        return fail(c, JANC_EINVAL, "mode must be JANC_CHEM_GENERIC or JANC_CHEM_SPECIALIZED");
+    if (mode == JANC_CHEM_SPECIALIZED && !c->chem_fn)
+        return fail(c, JANC_EINVAL, "no specialised chemistry kernel: %s",
+                    c->model != DETAILED ? "the model has no chemistry" : c->chem_log.c_str());
+    c->chem_mode = mode;
+    return JANC_OK;
+}
+
+janc_status janc_get_chem_kernel(const janc_ctx* c, int* mode) {
+    if (!c || !mode) return JANC_EINVAL;
+    *mode = c->chem_mode;
+    return JANC_OK;
+}
+
+janc_status janc_chem_kernel_check(const janc_mech* mech, char* log, int log_cap) {
+    janc_ctx tmp;   // host tables only
+    std::string msg;
+    janc_status st = build_mech(&tmp, mech);
+    if (st) msg = tmp.err;
+    std::vector<char> code;
+    if (!st && !chem_spec_code(chem_spec_source(tmp.hmech), &code, &msg)) st = JANC_EHIP;
+    if (log && log_cap > 0) {
+        const size_t n = std::min(msg.size(), (size_t)log_cap - 1);
+        std::memcpy(log, msg.data(), n);
+        log[n] = '\0';
+    }
+    return st;
+}
 
 janc_status janc_sync_status(janc_ctx* c, void* stream) {
     if (!c) return JANC_EINVAL;
@@ -1799,7 +1870,7 @@ janc_status janc_profile_step(janc_ctx* c, janc_plan* P, const janc_time* tm, do
     a.Uout = U;
     a.Tin = T;
     a.Tout = T;
-    if (e == hipSuccess && model == DETAILED) e = launch_chem(model, ns, P->tile_w, a, s);
+    if (e == hipSuccess && model == DETAILED) e = chem_launch(P->ctx, a, s);
     if (e == hipSuccess) e = hipEventRecord(ev[4], s);
     for (int l = P->maxlev; l >= 1 && e == hipSuccess; --l)
         e = launch_restrict(model, ns, a, P->dfine + P->fine_off[l], (int)P->fine[l].size(), s);

@@ -7,7 +7,6 @@
 
 namespace janc {
 
-constexpr int WG = 256;
 constexpr double WENO_EPS = 1e-6;
 
 // Read-only tables (domains, mechanism) viewed through the constant address

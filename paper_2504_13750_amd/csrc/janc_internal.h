@@ -13,6 +13,7 @@ constexpr int MAXS = 12;        // species
 constexpr int MAXR = 64;        // reactions
 constexpr int MAXP = 8;         // adjoint probes (JANC_MAX_PROBES)
 constexpr int MAXLIST = 3;      // reactant / product molecules per reaction
+constexpr int WG = 256;         // threads per workgroup of the tile and cell kernels
 constexpr double RU = 8.314472;     // J/(mol K), paper Sec. 4.1
 constexpr double PATM = 101325.0;   // Pa, Eq. 4.9
 

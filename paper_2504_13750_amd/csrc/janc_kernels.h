@@ -437,6 +437,67 @@ __global__ __launch_bounds__(WG) void init_kernel(StageArgs a) {
     publish_max3(a.red, 0, 2 * slot, 2 * slot + 1, 2 * a.red.nunits + B.domain, sx, sy, sc, scratch);
 }
 
+// (I - dt J) dU = dt w of the point-implicit step (Eq. 4.12-4.13) for the Jacobian J of
+// rho Y_1 .. rho Y_{Ns-1} and the production rates w: Gaussian elimination with partial
+// pivoting in registers; w returns the increment.
+template <int NS>
+__device__ __forceinline__ void chem_solve(double (&J)[NS - 1][NS - 1], double (&w)[NS - 1],
+                                           double dt, unsigned& st) {
+    constexpr int NT = NS - 1;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) J[k][q] = (k == q ? 1.0 : 0.0) - dt * J[k][q];
+        w[k] = w[k] * dt;
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+        // pivot row: the first row at or below c with the largest |entry| in column c;
+        // rows are exchanged by selects so that the matrix stays in registers, and only
+        // in wavefronts where some cell needs an exchange
+        int p = c;
+        double amax = fabs(J[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < NT; ++r) {
+            const double ar = fabs(J[r][c]);
+            if (ar > amax) { amax = ar; p = r; }
+        }
+        if (__any(p != c)) {
+#pragma unroll
+            for (int r = c + 1; r < NT; ++r) {
+                const bool sw = (r == p);
+#pragma unroll
+                for (int q = c; q < NT; ++q) {
+                    const double top = J[c][q], row = J[r][q];
+                    J[c][q] = sw ? row : top;
+                    J[r][q] = sw ? top : row;
+                }
+                const double wt = w[c], wr = w[r];
+                w[c] = sw ? wr : wt;
+                w[r] = sw ? wt : wr;
+            }
+        }
+        const double piv = J[c][c];
+        if (!(fabs(piv) > 0.0) || !isfinite(piv)) st |= STB_NONFINITE;
+        const double ip = 1.0 / piv;
+#pragma unroll
+        for (int r = c + 1; r < NT; ++r) {
+            const double fct = J[r][c] * ip;
+#pragma unroll
+            for (int q = c + 1; q < NT; ++q) J[r][q] -= fct * J[c][q];
+            w[r] -= fct * w[c];
+        }
+    }
+#pragma unroll
+    for (int r = NT - 1; r >= 0; --r) {
+        double sacc = w[r];
+#pragma unroll
+        for (int q = r + 1; q < NT; ++q) sacc -= J[r][q] * w[q];
+        w[r] = sacc / J[r][r];
+    }
+}
+
+
 // Point-implicit chemistry (Eq. 4.12-4.13) on rho Y_1 .. rho Y_{Ns-1} of each
 // solved cell, then Newton for the new T and the maxima for the next step.
 // Mechanism tables are read as wave-uniform scalar loads. Per-thread columns in
@@ -573,71 +634,16 @@ __device__ __forceinline__ void chem_cell(CMech* m, double* Xs, double* gts, dou
             for (int k = 0; k < NT; ++k) J[k][mm] += dSdT[k] * dTm;
         }
     }
-    // (I - dt J) dU = dt w, Gaussian elimination with partial pivoting, in place;
-    // w returns the increment of rho Y_1 .. rho Y_{Ns-1}
-#pragma unroll
-    for (int k = 0; k < NT; ++k) {
-#pragma unroll
-        for (int q = 0; q < NT; ++q) J[k][q] = (k == q ? 1.0 : 0.0) - dt * J[k][q];
-        w[k] = w[k] * dt;
-    }
-#pragma unroll
-    for (int c = 0; c < NT; ++c) {
-        // pivot row: the first row at or below c with the largest |entry| in column c;
-        // rows are exchanged by selects so that the matrix stays in registers, and only
-        // in wavefronts where some cell needs an exchange
-        int p = c;
-        double amax = fabs(J[c][c]);
-#pragma unroll
-        for (int r = c + 1; r < NT; ++r) {
-            const double ar = fabs(J[r][c]);
-            if (ar > amax) { amax = ar; p = r; }
-        }
-        if (__any(p != c)) {
-#pragma unroll
-            for (int r = c + 1; r < NT; ++r) {
-                const bool sw = (r == p);
-#pragma unroll
-                for (int q = c; q < NT; ++q) {
-                    const double top = J[c][q], row = J[r][q];
-                    J[c][q] = sw ? row : top;
-                    J[r][q] = sw ? top : row;
-                }
-                const double wt = w[c], wr = w[r];
-                w[c] = sw ? wr : wt;
-                w[r] = sw ? wt : wr;
-            }
-        }
-        const double piv = J[c][c];
-        if (!(fabs(piv) > 0.0) || !isfinite(piv)) st |= STB_NONFINITE;
-        const double ip = 1.0 / piv;
-#pragma unroll
-        for (int r = c + 1; r < NT; ++r) {
-            const double fct = J[r][c] * ip;
-#pragma unroll
-            for (int q = c + 1; q < NT; ++q) J[r][q] -= fct * J[c][q];
-            w[r] -= fct * w[c];
-        }
-    }
-#pragma unroll
-    for (int r = NT - 1; r >= 0; --r) {
-        double sacc = w[r];
-#pragma unroll
-        for (int q = r + 1; q < NT; ++q) sacc -= J[r][q] * w[q];
-        w[r] = sacc / J[r][r];
-    }
+    chem_solve<NS>(J, w, dt, st);
 }
 
-#ifndef CHEM_WAVES
-#define CHEM_WAVES 1
-#endif
-template <int NS, bool FULLJ>
-__global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
+// One chemistry launch over the tiles (one cell per thread): the dt of the phase, the
+// point-implicit step `cell(mech, rho, T, rho Y, dt, dY, status)` on each solved cell,
+// Newton for the new T, and the maxima for the next stage. Shared by the generic kernel
+// below and the kernel specialised at run time to a mechanism's structure.
+template <int NS, class Cell>
+__device__ __forceinline__ void chem_body(const StageArgs& a, double* scratch, Cell&& cell) {
     constexpr int NU = NS + 3;
-    __shared__ double Xs[(NS + 1) * WG];
-    __shared__ double gts[(NS + 1) * WG];
-    __shared__ double dqs[(NS + 1) * WG];
-    __shared__ double scratch[16];
     const Tile tile = a.tiles[blockIdx.x];
     const DevBlock B = a.blk[tile.block];
     CDom& D = cdom(a.dom, B.domain);
@@ -678,7 +684,7 @@ __global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
             for (int k = 0; k < NS - 1; ++k) rY[k] = a.Uout[(size_t)(4 + k) * a.pool + r.c];
             T = a.Tout[r.c];
         }
-        chem_cell<NS, FULLJ>(mech, Xs, gts, dqs, rho, T, rY, dt, dY, st);
+        cell(mech, rho, T, rY, dt, dY, st);
     }
     if (r.own) {
         double u[NU];
@@ -704,6 +710,21 @@ __global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
     }
     publish_max3(a.red, (phase == 1) ? 3 : 0, 2 * slot, 2 * slot + 1, 2 * a.red.nunits + B.domain, sx,
                  sy, sc, scratch);
+}
+
+#ifndef CHEM_WAVES
+#define CHEM_WAVES 1
+#endif
+template <int NS, bool FULLJ>
+__global__ __launch_bounds__(WG, CHEM_WAVES) void chem_kernel(StageArgs a) {
+    __shared__ double Xs[(NS + 1) * WG];
+    __shared__ double gts[(NS + 1) * WG];
+    __shared__ double dqs[(NS + 1) * WG];
+    __shared__ double scratch[16];
+    chem_body<NS>(a, scratch, [&](CMech* m, double rho, double T, const double (&rY)[NS - 1],
+                                  double dt, double (&dY)[NS - 1], unsigned& st) {
+        chem_cell<NS, FULLJ>(m, Xs, gts, dqs, rho, T, rY, dt, dY, st);
+    });
 }
 
 // Four-to-one restriction (Sec. 3.1.4 coarsening): each coarse cell under a
@@ -845,26 +866,9 @@ __global__ void prim_to_cons_kernel(const DevMech* mech, double gamma, double R,
     }
 }
 
-// ------------------------------------------------------------------ launch helpers
+// ------------------------------------------------------------------ launch shapes
 // Workgroups per block of the restriction and ring-fill launches (a 64 x 64 fine
 // block has 1024 coarse cells and 768 band cells: four workgroups of 256 threads).
 constexpr int RESTRICT_SPLIT = 4;
-
-template <int M, int NU>
-hipError_t launch_stage_m(int kind_mask, int tile_w, const StageArgs& a, int first,
-                                 int n, int owner, hipStream_t s) {
-    const bool h1 = kind_mask & 2, h2 = kind_mask & 1;
-#define JANC_STAGE(TXv, TYv)                                                                      \
-    do {                                                                                          \
-        if (h1 && h2) stage_kernel<M, NU, TXv, TYv, true, true><<<n, WG, 0, s>>>(a, first, owner);   \
-        else if (h1) stage_kernel<M, NU, TXv, TYv, true, false><<<n, WG, 0, s>>>(a, first, owner);  \
-        else stage_kernel<M, NU, TXv, TYv, false, true><<<n, WG, 0, s>>>(a, first, owner);          \
-    } while (0)
-    if (tile_w == 32) JANC_STAGE(32, 8);
-    else if (tile_w == 64) JANC_STAGE(64, 4);
-    else JANC_STAGE(16, 16);
-#undef JANC_STAGE
-    return hipGetLastError();
-}
 
 }  // namespace janc

@@ -1,7 +1,7 @@
 // janc_kernels.hip -- launchers of the JANC step kernels (janc_kernels.h): the
 // calorically perfect and one-step models here, the detailed model through the
 // per-species-count launch tables of janc_species.hip.
-#include "janc_kernels.h"
+#include "janc_launch.h"
 
 namespace janc {
 

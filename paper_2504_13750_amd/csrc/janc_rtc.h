@@ -1,0 +1,26 @@
+// janc_rtc.h -- run-time specialisation of the point-implicit chemistry kernel to the
+// structure of a mechanism (host side; see janc_rtc.hip).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "janc_internal.h"
+
+namespace janc {
+
+// Name of the specialised kernel in its code object.
+constexpr const char* CHEM_SPEC_KERNEL = "janc_chem_spec";
+
+// HIP source of the chemistry kernel specialised to d's structure: the reactants and
+// products of every reaction (species indices), reversibility, third-body reactions and
+// the non-zero stoichiometric changes become compile-time constants; every number of the
+// mechanism is still read from the device table. The arithmetic is the generic
+// kernel's, operation for operation.
+std::string chem_spec_source(const DevMech& d);
+
+// gfx950 code object of `src` (compiled with hipRTC once per distinct source in this
+// process); false with the compiler log in *log on failure.
+bool chem_spec_code(const std::string& src, std::vector<char>* code, std::string* log);
+
+}  // namespace janc

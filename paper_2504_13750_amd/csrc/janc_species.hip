@@ -3,7 +3,7 @@
 // restriction, ring refill, primitive-to-conserved conversion) and the discrete adjoint
 // (alpha, interface and cell reverses, chemistry reverse, loss terms, seeds, chain to the
 // primitives). janc_kernels.hip and janc_adjoint.hip reach them through species_ops().
-#include "janc_kernels.h"
+#include "janc_launch.h"
 #include "janc_adjoint.h"
 
 #ifndef JANC_NS
