@@ -285,6 +285,15 @@ def main():
         chem_ms.append(ms[3])
         restr_ms.append(ms[4])
         ring_ms.append(ms[5])
+    # the chemistry kernel specialised to the mechanism's structure (the default) against
+    # the generic one, same state and plan
+    chem_kernel = "specialized" if ctx.chem_kernel == janc.CHEM_SPECIALIZED else "generic"
+    chem_generic_ms = None
+    if chem_kernel == "specialized":
+        ctx.chem_kernel = janc.CHEM_GENERIC
+        chem_generic_ms = float(np.mean([ctx.profile_step(plan, tm, U, T, t)[3]
+                                         for _ in range(args.kernel_reps)]))
+        ctx.chem_kernel = janc.CHEM_SPECIALIZED
     ctx.sync_status()
     stage_avg = sum(stage_ms) / len(stage_ms)
     pst = plan.stats()
@@ -298,6 +307,9 @@ def main():
     log(f"[bench] stage kernel {stage_avg:.3f} ms avg: {achieved_tf:.2f} TFLOP/s FP64, "
         f"{achieved_gbs:.0f} GB/s algorithmic; chemistry {np.mean(chem_ms):.3f} ms, "
         f"restriction {np.mean(restr_ms):.3f} ms, ring {np.mean(ring_ms):.3f} ms")
+    if chem_generic_ms is not None:
+        log(f"[bench] chemistry kernel specialised to the mechanism {np.mean(chem_ms):.3f} ms, "
+            f"generic {chem_generic_ms:.3f} ms")
 
     # ------------------------------------------------------------ per-block launch form
     def _per_block():
@@ -551,13 +563,22 @@ def main():
         dadj()
         tfd = min(dfwd() for _ in range(3))
         tad = min(dadj() for _ in range(3))
+        # both runs with the generic chemistry kernels, for comparison
+        dctx.chem_kernel = janc.CHEM_GENERIC
+        dfwd()
+        dadj()
+        tfg = min(dfwd() for _ in range(3))
+        tag = min(dadj() for _ in range(3))
         dctx.sync_status()
         dctx.close()
         adjoint["detailed"] = {"workload": f"9-species front {dc.nx}x{dc.ny}, {dc.nsteps} steps, "
                                            f"checkpoints every {dk}",
-                               "forward_s": tfd, "adjoint_s": tad, "adjoint_over_forward": tad / tfd}
+                               "forward_s": tfd, "adjoint_s": tad, "adjoint_over_forward": tad / tfd,
+                               "generic_chemistry": {"forward_s": tfg, "adjoint_s": tag,
+                                                     "adjoint_over_forward": tag / tfg}}
         log(f"[bench] detailed-model adjoint {tad * 1e3:.2f} ms vs forward {tfd * 1e3:.2f} ms: "
-            f"{tad / tfd:.2f}x")
+            f"{tad / tfd:.2f}x (generic chemistry kernels: {tag * 1e3:.2f} vs {tfg * 1e3:.2f} ms, "
+            f"{tag / tfg:.2f}x)")
         return adjoint
     adjoint = None if args.no_adjoint else optional("adjoint", _adjoint)
 
@@ -642,7 +663,9 @@ def main():
             "binding_frac": max(achieved_tf / PEAK_FP64_VALU_TFLOPS, achieved_gbs / PEAK_HBM_GBS),
         },
         "kernels_ms": {"stage": stage_avg, "chemistry": float(np.mean(chem_ms)),
-                       "restriction": float(np.mean(restr_ms)), "ring": float(np.mean(ring_ms))},
+                       "restriction": float(np.mean(restr_ms)), "ring": float(np.mean(ring_ms)),
+                       "chemistry_generic": chem_generic_ms},
+        "chem_kernel": chem_kernel,
         "autotune": autotune,
         "per_block": per_block,
         "crossover": crossover,

@@ -39,8 +39,6 @@
 
 namespace janc {
 
-constexpr int AWG = 256;
-
 // Source of grid position (i, j) (one coordinate may lie in the 3 ghost layers).
 __device__ inline long long usrc(const AdjGrid& g, int i, int j, unsigned& fl) {
     fl = 0u;
@@ -793,6 +791,129 @@ __global__ __launch_bounds__(AWG) void adj_finish(AdjArgs A) {
 }
 
 // ------------------------------------------------------------------ chemistry in reverse
+// The reaction loops of the reversed chemistry step, the mechanism's structure read from
+// its table: the rates, S and J = dS/d(rho Y) of the forward step (rates), and the
+// reverse sweep that accumulates G = d/dX and GT = d/dT of mu . (dt S + dt J dU) (sweep).
+// The run-time specialised kernel supplies the same two loops with the structure
+// compiled in, the arithmetic unchanged.
+template <int NS>
+struct AdjReactions {
+    static constexpr int NT = NS - 1;
+    __device__ __forceinline__ void rates(CMech* m, const double (&X)[NS + 1], double lnT, double invT,
+                                          double lnC, const double (&gts)[NS + 1], double (&S)[NT],
+                                          double (&J)[NT][NT]) const {
+        const int nr = m->nr;
+        for (int i = 0; i < nr; ++i) {
+            const double lnkf = m->lnA[i] + m->b[i] * lnT - m->EaR[i] * invT;
+            const double kf = exp(lnkf);
+            double kb = 0.0;
+            if (m->rev[i]) {
+                double sg = 0.0;
+                for (int q = 0; q < MAXLIST; ++q) sg += gts[m->lb[i][q]] - gts[m->lf[i][q]];
+                kb = exp(lnkf + sg - (double)m->dnsum[i] * lnC);
+            }
+            const int f0 = m->lf[i][0], f1 = m->lf[i][1], f2 = m->lf[i][2];
+            const int r0 = m->lb[i][0], r1 = m->lb[i][1], r2 = m->lb[i][2];
+            const double Rf = kf * (X[f0] * X[f1] * X[f2]), Rb = kb * (X[r0] * X[r1] * X[r2]);
+            const bool tbr = m->has_tb[i] != 0;
+            double ctb = 1.0;
+            if (tbr) {
+                ctb = 0.0;
+#pragma unroll
+                for (int j = 0; j < NS; ++j) ctb += m->tb[i][j] * X[j];
+            }
+            const double q = ctb * (Rf - Rb);
+#pragma unroll
+            for (int k = 0; k < NT; ++k) S[k] += m->Mdnu[i][k] * q;
+            double dq[NS + 1];
+#pragma unroll
+            for (int j = 0; j <= NS; ++j) dq[j] = (tbr && j < NS) ? m->tb[i][j] * (Rf - Rb) : 0.0;
+            dq[f0] += ctb * kf * (X[f1] * X[f2]);
+            dq[f1] += ctb * kf * (X[f0] * X[f2]);
+            dq[f2] += ctb * kf * (X[f0] * X[f1]);
+            dq[r0] -= ctb * kb * (X[r1] * X[r2]);
+            dq[r1] -= ctb * kb * (X[r0] * X[r2]);
+            dq[r2] -= ctb * kb * (X[r0] * X[r1]);
+            const double dl = dq[NT] * m->invM[NT];
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                const double ck = m->Mdnu[i][k];
+                if (ck != 0.0) {
+#pragma unroll
+                    for (int q2 = 0; q2 < NT; ++q2) J[k][q2] += ck * (dq[q2] * m->invM[q2] - dl);
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void sweep(CMech* m, const double (&X)[NS + 1], const double (&dX)[NS + 1],
+                                          const double (&mu)[NT], double lnT, double invT, double lnC,
+                                          const double (&gts)[NS + 1], const double (&hm1)[NS + 1],
+                                          double (&G)[NS + 1], double& GT) const {
+        const int nr = m->nr;
+        for (int i = 0; i < nr; ++i) {
+            double ci = 0.0;
+#pragma unroll
+            for (int k = 0; k < NT; ++k) ci += mu[k] * m->Mdnu[i][k];
+            if (ci == 0.0) continue;
+            const double lnkf = m->lnA[i] + m->b[i] * lnT - m->EaR[i] * invT;
+            const double kf = exp(lnkf);
+            double kb = 0.0, dlb = 0.0;
+            const double dlf = (m->b[i] + m->EaR[i] * invT) * invT;   // d ln kf / dT
+            if (m->rev[i]) {
+                double sg = 0.0, sh = 0.0;
+                for (int q = 0; q < MAXLIST; ++q) {
+                    sg += gts[m->lb[i][q]] - gts[m->lf[i][q]];
+                    sh += hm1[m->lb[i][q]] - hm1[m->lf[i][q]];
+                }
+                kb = exp(lnkf + sg - (double)m->dnsum[i] * lnC);
+                dlb = dlf - sh * invT;                                  // d ln kb / dT
+            }
+            const int fs[3] = {m->lf[i][0], m->lf[i][1], m->lf[i][2]};
+            const int bs[3] = {m->lb[i][0], m->lb[i][1], m->lb[i][2]};
+            // R = k x0 x1 x2; dR/dx_s = k (product of the other two); dR . dX; its gradient
+            auto prod = [&](const int (&sl)[3], double kk, double& R, double (&dR)[3], double& dRd,
+                            double (&ddR)[3]) {
+                const double x0 = X[sl[0]], x1 = X[sl[1]], x2 = X[sl[2]];
+                const double e0 = dX[sl[0]], e1 = dX[sl[1]], e2 = dX[sl[2]];
+                R = kk * (x0 * x1 * x2);
+                dR[0] = kk * (x1 * x2);
+                dR[1] = kk * (x0 * x2);
+                dR[2] = kk * (x0 * x1);
+                dRd = dR[0] * e0 + dR[1] * e1 + dR[2] * e2;
+                ddR[0] = kk * (e1 * x2 + x1 * e2);
+                ddR[1] = kk * (e0 * x2 + x0 * e2);
+                ddR[2] = kk * (e0 * x1 + x0 * e1);
+            };
+            double Rf, dRf[3], dRfd, ddRf[3], Rb = 0.0, dRb[3] = {0.0, 0.0, 0.0}, dRbd = 0.0,
+                   ddRb[3] = {0.0, 0.0, 0.0};
+            prod(fs, kf, Rf, dRf, dRfd, ddRf);
+            if (m->rev[i]) prod(bs, kb, Rb, dRb, dRbd, ddRb);
+            const bool tbr = m->has_tb[i] != 0;
+            double ctb = 1.0, dctb = 0.0;
+            if (tbr) {
+                ctb = 0.0;
+#pragma unroll
+                for (int j = 0; j < NS; ++j) {
+                    ctb += m->tb[i][j] * X[j];
+                    dctb += m->tb[i][j] * dX[j];
+                }
+            }
+            // q = ctb (Rf - Rb); D = dq . dX = dctb (Rf - Rb) + ctb (dRf.dX - dRb.dX)
+            const double net = Rf - Rb, dnet = dRfd - dRbd;
+            if (tbr) {
+#pragma unroll
+                for (int j = 0; j < NS; ++j) G[j] += ci * m->tb[i][j] * (net + dnet);
+            }
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                G[fs[s]] += ci * ((ctb + dctb) * dRf[s] + ctb * ddRf[s]);
+                G[bs[s]] -= ci * ((ctb + dctb) * dRb[s] + ctb * ddRb[s]);
+            }
+            GT += ci * ((ctb + dctb) * (Rf * dlf - Rb * dlb) + ctb * (dRfd * dlf - dRbd * dlb));
+        }
+    }
+};
+
 // One cell per thread. The forward step is recomputed in registers (rates, the
 // Jacobian at frozen T and rho, the pivoted LU of I - dt J, the increment dU); then
 // mu = (I - dt J)^-T lambda_{rho Y}, c_i = sum_k mu_k M_k dnu_ik per reaction, and
@@ -800,8 +921,8 @@ __global__ __launch_bounds__(AWG) void adj_finish(AdjArgs A) {
 //   d/dX_l  += dt sum_i c_i (dq_i/dX_l + d(dq_i . dX)/dX_l)
 //   d/dT    += dt sum_i c_i (dq_i/dT + d(dq_i . dX)/dT)
 // then X -> (rho Y, rho) and T -> U* by the implicit-function theorem.
-template <int NS>
-__global__ __launch_bounds__(AWG) void adj_chem(AdjChemArgs A) {
+template <int NS, class Reactions>
+__device__ __forceinline__ void adj_chem_cell(const AdjChemArgs& A, const Reactions& rx) {
     constexpr int NT = NS - 1, NU = NS + 3;
     const long long c = (long long)blockIdx.x * AWG + threadIdx.x;
     if (c >= A.n) return;
@@ -848,48 +969,7 @@ __global__ __launch_bounds__(AWG) void adj_chem(AdjChemArgs A) {
 #pragma unroll
         for (int q = 0; q < NT; ++q) J[k][q] = 0.0;
     }
-    const int nr = m->nr;
-    for (int i = 0; i < nr; ++i) {
-        const double lnkf = m->lnA[i] + m->b[i] * lnT - m->EaR[i] * invT;
-        const double kf = exp(lnkf);
-        double kb = 0.0;
-        if (m->rev[i]) {
-            double sg = 0.0;
-            for (int q = 0; q < MAXLIST; ++q) sg += gts[m->lb[i][q]] - gts[m->lf[i][q]];
-            kb = exp(lnkf + sg - (double)m->dnsum[i] * lnC);
-        }
-        const int f0 = m->lf[i][0], f1 = m->lf[i][1], f2 = m->lf[i][2];
-        const int r0 = m->lb[i][0], r1 = m->lb[i][1], r2 = m->lb[i][2];
-        const double Rf = kf * (X[f0] * X[f1] * X[f2]), Rb = kb * (X[r0] * X[r1] * X[r2]);
-        const bool tbr = m->has_tb[i] != 0;
-        double ctb = 1.0;
-        if (tbr) {
-            ctb = 0.0;
-#pragma unroll
-            for (int j = 0; j < NS; ++j) ctb += m->tb[i][j] * X[j];
-        }
-        const double q = ctb * (Rf - Rb);
-#pragma unroll
-        for (int k = 0; k < NT; ++k) S[k] += m->Mdnu[i][k] * q;
-        double dq[NS + 1];
-#pragma unroll
-        for (int j = 0; j <= NS; ++j) dq[j] = (tbr && j < NS) ? m->tb[i][j] * (Rf - Rb) : 0.0;
-        dq[f0] += ctb * kf * (X[f1] * X[f2]);
-        dq[f1] += ctb * kf * (X[f0] * X[f2]);
-        dq[f2] += ctb * kf * (X[f0] * X[f1]);
-        dq[r0] -= ctb * kb * (X[r1] * X[r2]);
-        dq[r1] -= ctb * kb * (X[r0] * X[r2]);
-        dq[r2] -= ctb * kb * (X[r0] * X[r1]);
-        const double dl = dq[NT] * m->invM[NT];
-#pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            const double ck = m->Mdnu[i][k];
-            if (ck != 0.0) {
-#pragma unroll
-                for (int q2 = 0; q2 < NT; ++q2) J[k][q2] += ck * (dq[q2] * m->invM[q2] - dl);
-            }
-        }
-    }
+    rx.rates(m, X, lnT, invT, lnC, gts, S, J);
     // P (I - dt J) = L U, rows exchanged whole; L below the diagonal (unit diagonal)
     int piv[NT];
 #pragma unroll
@@ -995,67 +1075,7 @@ __global__ __launch_bounds__(AWG) void adj_chem(AdjChemArgs A) {
     double G[NS + 1], GT = 0.0;
 #pragma unroll
     for (int j = 0; j <= NS; ++j) G[j] = 0.0;
-    for (int i = 0; i < nr; ++i) {
-        double ci = 0.0;
-#pragma unroll
-        for (int k = 0; k < NT; ++k) ci += mu[k] * m->Mdnu[i][k];
-        if (ci == 0.0) continue;
-        const double lnkf = m->lnA[i] + m->b[i] * lnT - m->EaR[i] * invT;
-        const double kf = exp(lnkf);
-        double kb = 0.0, dlb = 0.0;
-        const double dlf = (m->b[i] + m->EaR[i] * invT) * invT;   // d ln kf / dT
-        if (m->rev[i]) {
-            double sg = 0.0, sh = 0.0;
-            for (int q = 0; q < MAXLIST; ++q) {
-                sg += gts[m->lb[i][q]] - gts[m->lf[i][q]];
-                sh += hm1[m->lb[i][q]] - hm1[m->lf[i][q]];
-            }
-            kb = exp(lnkf + sg - (double)m->dnsum[i] * lnC);
-            dlb = dlf - sh * invT;                                  // d ln kb / dT
-        }
-        const int fs[3] = {m->lf[i][0], m->lf[i][1], m->lf[i][2]};
-        const int bs[3] = {m->lb[i][0], m->lb[i][1], m->lb[i][2]};
-        // R = k x0 x1 x2; dR/dx_s = k (product of the other two); dR . dX; its gradient
-        auto prod = [&](const int (&sl)[3], double kk, double& R, double (&dR)[3], double& dRd,
-                        double (&ddR)[3]) {
-            const double x0 = X[sl[0]], x1 = X[sl[1]], x2 = X[sl[2]];
-            const double e0 = dX[sl[0]], e1 = dX[sl[1]], e2 = dX[sl[2]];
-            R = kk * (x0 * x1 * x2);
-            dR[0] = kk * (x1 * x2);
-            dR[1] = kk * (x0 * x2);
-            dR[2] = kk * (x0 * x1);
-            dRd = dR[0] * e0 + dR[1] * e1 + dR[2] * e2;
-            ddR[0] = kk * (e1 * x2 + x1 * e2);
-            ddR[1] = kk * (e0 * x2 + x0 * e2);
-            ddR[2] = kk * (e0 * x1 + x0 * e1);
-        };
-        double Rf, dRf[3], dRfd, ddRf[3], Rb = 0.0, dRb[3] = {0.0, 0.0, 0.0}, dRbd = 0.0,
-               ddRb[3] = {0.0, 0.0, 0.0};
-        prod(fs, kf, Rf, dRf, dRfd, ddRf);
-        if (m->rev[i]) prod(bs, kb, Rb, dRb, dRbd, ddRb);
-        const bool tbr = m->has_tb[i] != 0;
-        double ctb = 1.0, dctb = 0.0;
-        if (tbr) {
-            ctb = 0.0;
-#pragma unroll
-            for (int j = 0; j < NS; ++j) {
-                ctb += m->tb[i][j] * X[j];
-                dctb += m->tb[i][j] * dX[j];
-            }
-        }
-        // q = ctb (Rf - Rb); D = dq . dX = dctb (Rf - Rb) + ctb (dRf.dX - dRb.dX)
-        const double net = Rf - Rb, dnet = dRfd - dRbd;
-        if (tbr) {
-#pragma unroll
-            for (int j = 0; j < NS; ++j) G[j] += ci * m->tb[i][j] * (net + dnet);
-        }
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            G[fs[s]] += ci * ((ctb + dctb) * dRf[s] + ctb * ddRf[s]);
-            G[bs[s]] -= ci * ((ctb + dctb) * dRb[s] + ctb * ddRb[s]);
-        }
-        GT += ci * ((ctb + dctb) * (Rf * dlf - Rb * dlb) + ctb * (dRfd * dlf - dRbd * dlb));
-    }
+    rx.sweep(m, X, dX, mu, lnT, invT, lnC, gts, hm1, G, GT);
     // X_j = rho Y_j / M_j (j < NT), X_last = (rho - sum rho Y) / M_last
     double out[NU];
 #pragma unroll
@@ -1079,6 +1099,11 @@ __global__ __launch_bounds__(AWG) void adj_chem(AdjChemArgs A) {
 #pragma unroll
     for (int f = 0; f < NU; ++f) A.lamOut[(size_t)f * A.n + c] = out[f];
     if (st) atomicOr(A.status, st);
+}
+
+template <int NS>
+__global__ __launch_bounds__(AWG) void adj_chem(AdjChemArgs A) {
+    adj_chem_cell<NS>(A, AdjReactions<NS>{});
 }
 
 // Loss terms of a run of states: term[n0 + m - 1] = dt sum_q w_q p(U_m at cell_q)

@@ -57,6 +57,11 @@ struct janc_ctx {
     hipFunction_t chem_fn = nullptr;
     int chem_mode = JANC_CHEM_GENERIC;
     std::string chem_log;               // why no specialised kernel could be built
+    // its reverse in the adjoint, built at the first adjoint run that needs it
+    hipModule_t adj_chem_mod = nullptr;
+    hipFunction_t adj_chem_fn = nullptr;
+    bool adj_chem_tried = false;
+    std::string adj_chem_log;
 };
 
 struct GraphKey {
@@ -660,6 +665,36 @@ hipError_t chem_launch(janc_ctx* c, const StageArgs& a, hipStream_t s) {
     return launch_chem(c->model, c->ns, 0, a, s);
 }
 
+// The specialised reversed chemistry kernel of context c, compiled and loaded at the first
+// call (outside any stream capture: it runs before the adjoint's first launch). Where it
+// cannot be built the reason is kept and the generic kernel runs.
+void adj_chem_prepare(janc_ctx* c) {
+    if (c->adj_chem_tried || c->model != DETAILED) return;
+    c->adj_chem_tried = true;
+    std::vector<char> code;
+    if (!chem_spec_code(adj_chem_spec_source(c->hmech), &code, &c->adj_chem_log)) return;
+    if (hipModuleLoadData(&c->adj_chem_mod, code.data()) != hipSuccess ||
+        hipModuleGetFunction(&c->adj_chem_fn, c->adj_chem_mod, ADJ_CHEM_SPEC_KERNEL) != hipSuccess) {
+        c->adj_chem_log = "loading the specialised adjoint chemistry kernel failed";
+        if (c->adj_chem_mod) hipModuleUnload(c->adj_chem_mod);
+        c->adj_chem_mod = nullptr;
+        c->adj_chem_fn = nullptr;
+    }
+}
+
+// The adjoint chemistry launch of context c: specialised when the chemistry kernel
+// selection is, and it is built; else the generic kernel.
+hipError_t adj_chem_run(janc_ctx* c, const AdjChemArgs& A, hipStream_t s) {
+    if (c->chem_mode == JANC_CHEM_SPECIALIZED && c->adj_chem_fn) {
+        if (A.n <= 0) return hipSuccess;
+        AdjChemArgs arg = A;
+        void* params[] = {&arg};
+        const unsigned nb = (unsigned)((A.n + AWG - 1) / AWG);
+        return hipModuleLaunchKernel(c->adj_chem_fn, nb, 1, 1, AWG, 1, 1, 0, s, params, nullptr);
+    }
+    return adj_chem_launch(c->ns, A, s);
+}
+
 // The first half chemistry launch of a Strang-split step (in place on U, T).
 hipError_t launch_chem_first_half(janc_plan* P, const StageArgs& base, const Reduce& red, double* U,
                                   double* T, int first_tile, int ntiles, int xfirst, hipStream_t s) {
@@ -1131,6 +1166,7 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
         return fail(c, JANC_EINVAL, "adjoint grid needs nx >= 3 and ny = 1 or ny >= 3");
     const long long n = (long long)g->nx * g->ny;
     if (n > (1ll << 31) - 1) return fail(c, JANC_EINVAL, "grid too large for the adjoint");
+    if (det && c->chem_mode == JANC_CHEM_SPECIALIZED) adj_chem_prepare(c);
     if (np < 0 || np > JANC_MAX_PROBES) return fail(c, JANC_EINVAL, "between 0 and %d probes", JANC_MAX_PROBES);
     for (int q = 0; q < np; ++q)
         if (pc[q] < 0 || pc[q] >= n) return fail(c, JANC_EINVAL, "probe cell %d out of range", q);
@@ -1413,7 +1449,7 @@ janc_status run_adjoint(janc_ctx* c, const janc_grid* g, const janc_physics* ph,
                 ac.lamOut = lC;
                 ac.dt = dt;
                 ac.status = c->dstatus;
-                HIPCHK(c, adj_chem_launch(ns, ac, s), "adjoint chemistry");
+                HIPCHK(c, adj_chem_run(c, ac, s), "adjoint chemistry");
                 lw3 = lC;
             }
             AdjArgs a3 = A;   // stage 3: W = U/3 + 2/3 (V + dt L(V)), V = U^(2)
@@ -1665,6 +1701,7 @@ void janc_destroy(janc_ctx* c) {
         if (e) hipEventDestroy(e);
     if (c->adj_stream) hipStreamDestroy(c->adj_stream);
     if (c->chem_mod) hipModuleUnload(c->chem_mod);
+    if (c->adj_chem_mod) hipModuleUnload(c->adj_chem_mod);
     delete c;
 }
 
@@ -1696,6 +1733,7 @@ janc_status janc_chem_kernel_check(const janc_mech* mech, char* log, int log_cap
     if (st) msg = tmp.err;
     std::vector<char> code;
     if (!st && !chem_spec_code(chem_spec_source(tmp.hmech), &code, &msg)) st = JANC_EHIP;
+    if (!st && !chem_spec_code(adj_chem_spec_source(tmp.hmech), &code, &msg)) st = JANC_EHIP;
     if (log && log_cap > 0) {
         const size_t n = std::min(msg.size(), (size_t)log_cap - 1);
         std::memcpy(log, msg.data(), n);

@@ -14,6 +14,7 @@ constexpr int MAXR = 64;        // reactions
 constexpr int MAXP = 8;         // adjoint probes (JANC_MAX_PROBES)
 constexpr int MAXLIST = 3;      // reactant / product molecules per reaction
 constexpr int WG = 256;         // threads per workgroup of the tile and cell kernels
+constexpr int AWG = 256;        // threads per workgroup of the adjoint kernels
 constexpr double RU = 8.314472;     // J/(mol K), paper Sec. 4.1
 constexpr double PATM = 101325.0;   // Pa, Eq. 4.9
 

@@ -1,4 +1,4 @@
-// janc_rtc.h -- run-time specialisation of the point-implicit chemistry kernel to the
+// janc_rtc.h -- run-time specialisation of the point-implicit chemistry kernels to the
 // structure of a mechanism (host side; see janc_rtc.hip).
 #pragma once
 
@@ -9,8 +9,9 @@
 
 namespace janc {
 
-// Name of the specialised kernel in its code object.
+// Names of the specialised kernels in their code objects.
 constexpr const char* CHEM_SPEC_KERNEL = "janc_chem_spec";
+constexpr const char* ADJ_CHEM_SPEC_KERNEL = "janc_adj_chem_spec";
 
 // HIP source of the chemistry kernel specialised to d's structure: the reactants and
 // products of every reaction (species indices), reversibility, third-body reactions and
@@ -18,6 +19,12 @@ constexpr const char* CHEM_SPEC_KERNEL = "janc_chem_spec";
 // mechanism is still read from the device table. The arithmetic is the generic
 // kernel's, operation for operation.
 std::string chem_spec_source(const DevMech& d);
+
+// HIP source of the reversed chemistry kernel of the discrete adjoint (adj_chem) specialised
+// the same way: the rate, Jacobian and reverse-sweep loops over the reactions unrolled with
+// the species indices, reversibility and third-body pattern as constants. The arithmetic is
+// the generic adj_chem's, operation for operation.
+std::string adj_chem_spec_source(const DevMech& d);
 
 // gfx950 code object of `src` (compiled with hipRTC once per distinct source in this
 // process); false with the compiler log in *log on failure.

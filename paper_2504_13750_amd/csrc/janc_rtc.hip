@@ -1,4 +1,5 @@
-// janc_rtc.hip -- the chemistry kernel specialised at run time to a mechanism's structure.
+// janc_rtc.hip -- the chemistry kernels specialised at run time to a mechanism's structure:
+// the point-implicit step of the forward path and its reverse in the discrete adjoint.
 //
 // The generic kernel (chem_cell in janc_kernels.h) reads the species of each reaction
 // from the mechanism table, so it keeps X, the Gibbs terms and the derivative row dq/dX
@@ -101,6 +102,135 @@ std::string chem_spec_source(const DevMech& d) {
       << ">(a, scratch, [&](janc::CMech* m, double rho, double T, const double (&rY)[" << nt
       << "], double dt, double (&dY)[" << nt << "], unsigned& st) {\n"
          "        janc::chem_cell_spec(m, rho, T, rY, dt, dY, st);\n    });\n}\n";
+    return o.str();
+}
+
+std::string adj_chem_spec_source(const DevMech& d) {
+    const int ns = d.ns, nr = d.nr, nt = ns - 1;
+    const std::string NS = std::to_string(ns), NT = std::to_string(nt);
+    std::ostringstream o;
+    o << "// reversed chemistry cell step specialised to a mechanism of " << ns << " species and " << nr
+      << " reactions\n#include \"janc_adjoint.h\"\nnamespace janc {\nstruct AdjReactionsSpec {\n";
+    // the forward rates, S and J (AdjReactions::rates with the structure compiled in)
+    o << "    __device__ __forceinline__ void rates(CMech* m, const double (&X)[" << ns + 1
+      << "], double lnT, double invT, double lnC, const double (&gts)[" << ns + 1 << "], double (&S)[" << NT
+      << "], double (&J)[" << NT << "][" << NT << "]) const {\n";
+    for (int i = 0; i < nr; ++i) {
+        const int* f = d.lf[i];
+        const int* b = d.lb[i];
+        const std::string I = std::to_string(i);
+        o << "        {  // reaction " << i << "\n";
+        o << "            const double lnkf = m->lnA[" << I << "] + m->b[" << I << "] * lnT - m->EaR[" << I << "] * invT;\n";
+        o << "            const double kf = exp(lnkf);\n            double kb = 0.0;\n";
+        if (d.rev[i]) {
+            o << "            {\n                double sg = 0.0;\n";
+            for (int q = 0; q < MAXLIST; ++q)
+                o << "                sg += gts[" << b[q] << "] - gts[" << f[q] << "];\n";
+            o << "                kb = exp(lnkf + sg - (double)m->dnsum[" << I << "] * lnC);\n            }\n";
+        }
+        o << "            const double Rf = kf * (X[" << f[0] << "] * X[" << f[1] << "] * X[" << f[2]
+          << "]), Rb = kb * (X[" << b[0] << "] * X[" << b[1] << "] * X[" << b[2] << "]);\n";
+        if (d.has_tb[i]) {
+            o << "            double ctb = 0.0;\n";
+            for (int j = 0; j < ns; ++j) o << "            ctb += m->tb[" << I << "][" << j << "] * X[" << j << "];\n";
+        } else {
+            o << "            const double ctb = 1.0;\n";
+        }
+        o << "            const double q = ctb * (Rf - Rb);\n";
+        for (int k = 0; k < nt; ++k) o << "            S[" << k << "] += m->Mdnu[" << I << "][" << k << "] * q;\n";
+        o << "            double dq[" << ns + 1 << "];\n";
+        for (int j = 0; j <= ns; ++j) {
+            if (d.has_tb[i] && j < ns) o << "            dq[" << j << "] = m->tb[" << I << "][" << j << "] * (Rf - Rb);\n";
+            else o << "            dq[" << j << "] = 0.0;\n";
+        }
+        o << "            dq[" << f[0] << "] += ctb * kf * (X[" << f[1] << "] * X[" << f[2] << "]);\n";
+        o << "            dq[" << f[1] << "] += ctb * kf * (X[" << f[0] << "] * X[" << f[2] << "]);\n";
+        o << "            dq[" << f[2] << "] += ctb * kf * (X[" << f[0] << "] * X[" << f[1] << "]);\n";
+        o << "            dq[" << b[0] << "] -= ctb * kb * (X[" << b[1] << "] * X[" << b[2] << "]);\n";
+        o << "            dq[" << b[1] << "] -= ctb * kb * (X[" << b[0] << "] * X[" << b[2] << "]);\n";
+        o << "            dq[" << b[2] << "] -= ctb * kb * (X[" << b[0] << "] * X[" << b[1] << "]);\n";
+        o << "            const double dl = dq[" << nt << "] * m->invM[" << nt << "];\n";
+        for (int k = 0; k < nt; ++k) {
+            if (d.dnu[i][k] == 0) continue;
+            for (int q2 = 0; q2 < nt; ++q2)
+                o << "            J[" << k << "][" << q2 << "] += m->Mdnu[" << I << "][" << k << "] * (dq[" << q2
+                  << "] * m->invM[" << q2 << "] - dl);\n";
+        }
+        o << "        }\n";
+    }
+    o << "    }\n";
+    // the reverse sweep (AdjReactions::sweep with the structure compiled in)
+    o << "    __device__ __forceinline__ void sweep(CMech* m, const double (&X)[" << ns + 1
+      << "], const double (&dX)[" << ns + 1 << "], const double (&mu)[" << NT
+      << "], double lnT, double invT, double lnC, const double (&gts)[" << ns + 1 << "], const double (&hm1)["
+      << ns + 1 << "], double (&G)[" << ns + 1 << "], double& GT) const {\n";
+    for (int i = 0; i < nr; ++i) {
+        const int* f = d.lf[i];
+        const int* b = d.lb[i];
+        const std::string I = std::to_string(i);
+        o << "        {  // reaction " << i << "\n            double ci = 0.0;\n";
+        for (int k = 0; k < nt; ++k) o << "            ci += mu[" << k << "] * m->Mdnu[" << I << "][" << k << "];\n";
+        o << "            if (ci != 0.0) {\n";
+        o << "                const double lnkf = m->lnA[" << I << "] + m->b[" << I << "] * lnT - m->EaR[" << I << "] * invT;\n";
+        o << "                const double kf = exp(lnkf);\n                double kb = 0.0, dlb = 0.0;\n";
+        o << "                const double dlf = (m->b[" << I << "] + m->EaR[" << I << "] * invT) * invT;\n";
+        if (d.rev[i]) {
+            o << "                {\n                    double sg = 0.0, sh = 0.0;\n";
+            for (int q = 0; q < MAXLIST; ++q) {
+                o << "                    sg += gts[" << b[q] << "] - gts[" << f[q] << "];\n";
+                o << "                    sh += hm1[" << b[q] << "] - hm1[" << f[q] << "];\n";
+            }
+            o << "                    kb = exp(lnkf + sg - (double)m->dnsum[" << I << "] * lnC);\n";
+            o << "                    dlb = dlf - sh * invT;\n                }\n";
+        }
+        // R = k x0 x1 x2, dR/dx_s, dR . dX and its gradient, for the reactants (F) and,
+        // if reversible, the products (B); zero otherwise
+        auto prod = [&](const char* P, const int* sl, const char* kk) {
+            o << "                const double " << P << "x0 = X[" << sl[0] << "], " << P << "x1 = X[" << sl[1] << "], "
+              << P << "x2 = X[" << sl[2] << "];\n";
+            o << "                const double " << P << "e0 = dX[" << sl[0] << "], " << P << "e1 = dX[" << sl[1] << "], "
+              << P << "e2 = dX[" << sl[2] << "];\n";
+            o << "                const double R" << P << " = " << kk << " * (" << P << "x0 * " << P << "x1 * " << P << "x2);\n";
+            o << "                const double dR" << P << "0 = " << kk << " * (" << P << "x1 * " << P << "x2), dR" << P
+              << "1 = " << kk << " * (" << P << "x0 * " << P << "x2), dR" << P << "2 = " << kk << " * (" << P << "x0 * "
+              << P << "x1);\n";
+            o << "                const double dR" << P << "d = dR" << P << "0 * " << P << "e0 + dR" << P << "1 * " << P
+              << "e1 + dR" << P << "2 * " << P << "e2;\n";
+            o << "                const double ddR" << P << "0 = " << kk << " * (" << P << "e1 * " << P << "x2 + " << P
+              << "x1 * " << P << "e2), ddR" << P << "1 = " << kk << " * (" << P << "e0 * " << P << "x2 + " << P << "x0 * "
+              << P << "e2), ddR" << P << "2 = " << kk << " * (" << P << "e0 * " << P << "x1 + " << P << "x0 * " << P
+              << "e1);\n";
+        };
+        prod("F", f, "kf");
+        if (d.rev[i]) {
+            prod("B", b, "kb");
+        } else {
+            o << "                const double RB = 0.0, dRB0 = 0.0, dRB1 = 0.0, dRB2 = 0.0, dRBd = 0.0, ddRB0 = 0.0, "
+                 "ddRB1 = 0.0, ddRB2 = 0.0;\n";
+        }
+        if (d.has_tb[i]) {
+            o << "                double ctb = 0.0, dctb = 0.0;\n";
+            for (int j = 0; j < ns; ++j) {
+                o << "                ctb += m->tb[" << I << "][" << j << "] * X[" << j << "];\n";
+                o << "                dctb += m->tb[" << I << "][" << j << "] * dX[" << j << "];\n";
+            }
+        } else {
+            o << "                const double ctb = 1.0, dctb = 0.0;\n";
+        }
+        o << "                const double net = RF - RB, dnet = dRFd - dRBd;\n";
+        if (d.has_tb[i])
+            for (int j = 0; j < ns; ++j)
+                o << "                G[" << j << "] += ci * m->tb[" << I << "][" << j << "] * (net + dnet);\n";
+        for (int q = 0; q < 3; ++q) {
+            o << "                G[" << f[q] << "] += ci * ((ctb + dctb) * dRF" << q << " + ctb * ddRF" << q << ");\n";
+            o << "                G[" << b[q] << "] -= ci * ((ctb + dctb) * dRB" << q << " + ctb * ddRB" << q << ");\n";
+        }
+        o << "                GT += ci * ((ctb + dctb) * (RF * dlf - RB * dlb) + ctb * (dRFd * dlf - dRBd * dlb));\n";
+        o << "            }\n        }\n";
+    }
+    o << "    }\n};\n}  // namespace janc\n";
+    o << "extern \"C\" __global__ __launch_bounds__(janc::AWG) void " << ADJ_CHEM_SPEC_KERNEL
+      << "(janc::AdjChemArgs A) {\n    janc::adj_chem_cell<" << ns << ">(A, janc::AdjReactionsSpec{});\n}\n";
     return o.str();
 }
 

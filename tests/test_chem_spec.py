@@ -1,10 +1,11 @@
-"""The chemistry kernel specialised to a mechanism's structure (janc_rtc.hip) is generated
-and compiled with hipRTC for gfx950 on the host (no device needed) for mechanisms of
+"""The chemistry kernels specialised to a mechanism's structure (janc_rtc.hip: the forward
+point-implicit step and its reverse in the adjoint) are generated and compiled with hipRTC
+for gfx950 on the host (no device needed) for mechanisms of
 different shapes: the seeded 9-species mechanism (one and two NASA-7 ranges), the
 30-reaction complete mechanism, the hand-written 6-species chemkin mechanism, a
 12-species mechanism with inert species, and a 2-species mechanism with an irreversible
-reaction of a repeated reactant; a mechanism without kernels is rejected. Its results are
-checked against the generic kernel on the GPU (test_gpu_chem_spec.py)."""
+reaction of a repeated reactant; a mechanism without kernels is rejected. Their results are
+checked against the generic kernels on the GPU (test_gpu_chem_spec.py)."""
 
 import copy
 
