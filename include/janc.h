@@ -125,9 +125,8 @@ typedef struct janc_ctx janc_ctx;
 
 /* Create a context on HIP device `device` for one model. mech is required for
  * JANC_MODEL_DETAILED and ignored otherwise. For the detailed model the context also
- * compiles (hipRTC, once per distinct mechanism structure in the process) the
- * point-implicit chemistry kernel specialised to the mechanism; see
- * janc_set_chem_kernel. */
+ * compiles (hipRTC, once per distinct mechanism in the process) the point-implicit
+ * chemistry kernel specialised to the mechanism; see janc_set_chem_kernel. */
 janc_status janc_create(janc_ctx **out, int model, const janc_mech *mech, int device);
 void janc_destroy(janc_ctx *ctx);
 const char *janc_last_error(const janc_ctx *ctx);
@@ -139,17 +138,19 @@ int janc_num_fields(const janc_ctx *ctx);
  * table (per-thread LDS columns indexed by those species numbers). JANC_CHEM_SPECIALIZED
  * (the default once it is built): the same arithmetic, operation for operation, with the
  * mechanism's structure -- participants of every reaction, reversibility, third-body
- * reactions, non-zero stoichiometric changes -- compiled in as constants, so that the
- * cell's state lives in registers; the mechanism's numbers are still read from its device
- * table, and the results equal the generic kernel's bitwise. The species + T Jacobian
+ * reactions, non-zero stoichiometric changes -- and its rate, stoichiometric, third-body
+ * and molar-mass numbers compiled in as constants (exact literals), so that the cell's
+ * state lives in registers; the results equal the generic kernel's bitwise. The adjoint's
+ * reversed chemistry step (janc_adjoint) follows the same selection. The species + T Jacobian
  * (JANC_JAC_FULL) always uses the generic kernel. Selecting JANC_CHEM_SPECIALIZED where it
  * could not be built is JANC_EINVAL (janc_last_error gives the compiler's reason). */
 enum { JANC_CHEM_GENERIC = 0, JANC_CHEM_SPECIALIZED = 1 };
 janc_status janc_set_chem_kernel(janc_ctx *ctx, int mode);
 janc_status janc_get_chem_kernel(const janc_ctx *ctx, int *mode);
 
-/* Generates and compiles (hipRTC, no device needed) the specialised chemistry kernel of
- * a mechanism, as janc_create does: JANC_OK, or JANC_EINVAL for a mechanism janc_create
+/* Generates and compiles (hipRTC, no device needed) the specialised chemistry kernels of
+ * a mechanism (the forward step, as janc_create does, and the adjoint's reversed step, as
+ * the first janc_adjoint does): JANC_OK, or JANC_EINVAL for a mechanism janc_create
  * rejects, or JANC_EHIP with the compiler log in log (host, log_cap bytes incl. the
  * terminating zero; may be NULL). */
 janc_status janc_chem_kernel_check(const janc_mech *mech, char *log, int log_cap);

@@ -7,12 +7,16 @@
 // a loop with wave-uniform branches. With the structure known when the source is
 // compiled, those indices are constants: the same arithmetic, in the same order, runs on
 // registers, and every reaction's rates can be scheduled ahead of the previous one's
-// Jacobian update. Only the point-implicit cell step differs; the launch body
+// Jacobian update. The mechanism's numbers become exact hexadecimal literals (no scalar
+// loads and waits for them), except the NASA-7 coefficients, whose products with the
+// polynomial's constant factors would otherwise be folded at compile time and round
+// differently from the generic kernel. Only the point-implicit cell step differs; the launch body
 // (chem_body) and the solve (chem_solve) are the generic kernel's own code, compiled
 // from the same headers (their texts are embedded in the library at build time).
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <cstdio>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -26,6 +30,12 @@ namespace {
 
 std::string xs(int j, int ns) { return j >= ns ? std::string("1.0") : "X[" + std::to_string(j) + "]"; }
 std::string gs(int j, int ns) { return j >= ns ? std::string("0.0") : "g[" + std::to_string(j) + "]"; }
+// A number of the mechanism as an exact hexadecimal literal.
+std::string lit(double v) {
+    char buf[48];
+    std::snprintf(buf, sizeof buf, "(%a)", v);
+    return buf;
+}
 }  // namespace
 
 std::string chem_spec_source(const DevMech& d) {
@@ -36,10 +46,13 @@ std::string chem_spec_source(const DevMech& d) {
     o << "__device__ __forceinline__ void chem_cell_spec(CMech* m, double rho, double T, const double (&rY)["
       << nt << "], double dt, double (&w)[" << nt << "], unsigned& st) {\n";
     o << "    double X[" << ns << "];\n    double s = 0.0;\n";
-    for (int j = 0; j < nt; ++j) o << "    X[" << j << "] = rY[" << j << "] * m->invM[" << j << "];\n    s += rY[" << j << "];\n";
-    o << "    X[" << nt << "] = (rho - s) * m->invM[" << nt << "];\n";
+    for (int j = 0; j < nt; ++j) o << "    X[" << j << "] = rY[" << j << "] * " << lit(d.invM[j]) << ";\n    s += rY[" << j << "];\n";
+    o << "    X[" << nt << "] = (rho - s) * " << lit(d.invM[nt]) << ";\n";
     o << "    const double lnT = log(T), invT = 1.0 / T;\n";
     o << "    const double lnC = log(PATM / RU) - lnT;\n";
+    // the NASA-7 coefficients stay table reads: as literals, their products with the
+    // polynomial's constant factors would be folded at compile time (rounded once, where
+    // the generic kernel fuses them into the next multiply-add)
     o << "    double g[" << ns << "];\n#pragma unroll\n    for (int j = 0; j < " << ns << "; ++j) {\n"
          "        const bool hi = m->two_range && T >= m->tmid[j];\n        double a[7];\n#pragma unroll\n"
          "        for (int q = 0; q < 7; ++q) a[q] = hi ? m->nasa_hi[j][q] : m->nasa[j][q];\n"
@@ -53,12 +66,12 @@ std::string chem_spec_source(const DevMech& d) {
         const int* f = d.lf[i];
         const int* b = d.lb[i];
         o << "    {  // reaction " << i << "\n";
-        o << "        const double lnkf = m->lnA[" << i << "] + m->b[" << i << "] * lnT - m->EaR[" << i << "] * invT;\n";
+        o << "        const double lnkf = " << lit(d.lnA[i]) << " + " << lit(d.b[i]) << " * lnT - " << lit(d.EaR[i]) << " * invT;\n";
         o << "        const double kf = exp(lnkf);\n";
         if (d.rev[i]) {
             o << "        const double sg = (" << gs(b[0], ns) << " + " << gs(b[1], ns) << " + " << gs(b[2], ns) << ") - ("
               << gs(f[0], ns) << " + " << gs(f[1], ns) << " + " << gs(f[2], ns) << ");\n";
-            o << "        const double kb = exp(lnkf + sg - (double)m->dnsum[" << i << "] * lnC);\n";
+            o << "        const double kb = exp(lnkf + sg - " << lit((double)d.dnsum[i]) << " * lnC);\n";
         } else {
             o << "        const double kb = 0.0;\n";
         }
@@ -67,16 +80,16 @@ std::string chem_spec_source(const DevMech& d) {
         o << "        const double Rf = kf * (xf0 * xf1 * xf2), Rb = kb * (xb0 * xb1 * xb2);\n";
         if (d.has_tb[i]) {
             o << "        double ctb = 0.0;\n";
-            for (int j = 0; j < ns; ++j) o << "        ctb += m->tb[" << i << "][" << j << "] * X[" << j << "];\n";
+            for (int j = 0; j < ns; ++j) o << "        ctb += " << lit(d.tb[i][j]) << " * X[" << j << "];\n";
         } else {
             o << "        const double ctb = 1.0;\n";
         }
         o << "        const double net = Rf - Rb;\n        const double q = ctb * net;\n";
-        for (int k = 0; k < nt; ++k) o << "        w[" << k << "] += m->Mdnu[" << i << "][" << k << "] * q;\n";
+        for (int k = 0; k < nt; ++k) o << "        w[" << k << "] += " << lit(d.Mdnu[i][k]) << " * q;\n";
         o << "        double dq[" << ns + 1 << "];\n";
         for (int j = 0; j <= ns; ++j) {
             o << "        dq[" << j << "] = ";
-            if (d.has_tb[i] && j < ns) o << "m->tb[" << i << "][" << j << "] * net;\n";
+            if (d.has_tb[i] && j < ns) o << "" << lit(d.tb[i][j]) << " * net;\n";
             else o << "0.0;\n";
         }
         o << "        const double cf = ctb * kf, cb = ctb * kb;\n";
@@ -86,13 +99,13 @@ std::string chem_spec_source(const DevMech& d) {
         o << "        dq[" << b[0] << "] -= cb * (xb1 * xb2);\n";
         o << "        dq[" << b[1] << "] -= cb * (xb0 * xb2);\n";
         o << "        dq[" << b[2] << "] -= cb * (xb0 * xb1);\n";
-        o << "        const double dlast = dq[" << nt << "] * m->invM[" << nt << "];\n";
+        o << "        const double dlast = dq[" << nt << "] * " << lit(d.invM[nt]) << ";\n";
         o << "        double Dm[" << nt << "];\n";
-        for (int mm = 0; mm < nt; ++mm) o << "        Dm[" << mm << "] = dq[" << mm << "] * m->invM[" << mm << "] - dlast;\n";
+        for (int mm = 0; mm < nt; ++mm) o << "        Dm[" << mm << "] = dq[" << mm << "] * " << lit(d.invM[mm]) << " - dlast;\n";
         for (int k = 0; k < nt; ++k) {
             if (d.dnu[i][k] == 0) continue;
             for (int mm = 0; mm < nt; ++mm)
-                o << "        J[" << k << "][" << mm << "] += m->Mdnu[" << i << "][" << k << "] * Dm[" << mm << "];\n";
+                o << "        J[" << k << "][" << mm << "] += " << lit(d.Mdnu[i][k]) << " * Dm[" << mm << "];\n";
         }
         o << "    }\n";
     }
@@ -120,27 +133,27 @@ std::string adj_chem_spec_source(const DevMech& d) {
         const int* b = d.lb[i];
         const std::string I = std::to_string(i);
         o << "        {  // reaction " << i << "\n";
-        o << "            const double lnkf = m->lnA[" << I << "] + m->b[" << I << "] * lnT - m->EaR[" << I << "] * invT;\n";
+        o << "            const double lnkf = " << lit(d.lnA[i]) << " + " << lit(d.b[i]) << " * lnT - " << lit(d.EaR[i]) << " * invT;\n";
         o << "            const double kf = exp(lnkf);\n            double kb = 0.0;\n";
         if (d.rev[i]) {
             o << "            {\n                double sg = 0.0;\n";
             for (int q = 0; q < MAXLIST; ++q)
                 o << "                sg += gts[" << b[q] << "] - gts[" << f[q] << "];\n";
-            o << "                kb = exp(lnkf + sg - (double)m->dnsum[" << I << "] * lnC);\n            }\n";
+            o << "                kb = exp(lnkf + sg - " << lit((double)d.dnsum[i]) << " * lnC);\n            }\n";
         }
         o << "            const double Rf = kf * (X[" << f[0] << "] * X[" << f[1] << "] * X[" << f[2]
           << "]), Rb = kb * (X[" << b[0] << "] * X[" << b[1] << "] * X[" << b[2] << "]);\n";
         if (d.has_tb[i]) {
             o << "            double ctb = 0.0;\n";
-            for (int j = 0; j < ns; ++j) o << "            ctb += m->tb[" << I << "][" << j << "] * X[" << j << "];\n";
+            for (int j = 0; j < ns; ++j) o << "            ctb += " << lit(d.tb[i][j]) << " * X[" << j << "];\n";
         } else {
             o << "            const double ctb = 1.0;\n";
         }
         o << "            const double q = ctb * (Rf - Rb);\n";
-        for (int k = 0; k < nt; ++k) o << "            S[" << k << "] += m->Mdnu[" << I << "][" << k << "] * q;\n";
+        for (int k = 0; k < nt; ++k) o << "            S[" << k << "] += " << lit(d.Mdnu[i][k]) << " * q;\n";
         o << "            double dq[" << ns + 1 << "];\n";
         for (int j = 0; j <= ns; ++j) {
-            if (d.has_tb[i] && j < ns) o << "            dq[" << j << "] = m->tb[" << I << "][" << j << "] * (Rf - Rb);\n";
+            if (d.has_tb[i] && j < ns) o << "            dq[" << j << "] = " << lit(d.tb[i][j]) << " * (Rf - Rb);\n";
             else o << "            dq[" << j << "] = 0.0;\n";
         }
         o << "            dq[" << f[0] << "] += ctb * kf * (X[" << f[1] << "] * X[" << f[2] << "]);\n";
@@ -149,12 +162,12 @@ std::string adj_chem_spec_source(const DevMech& d) {
         o << "            dq[" << b[0] << "] -= ctb * kb * (X[" << b[1] << "] * X[" << b[2] << "]);\n";
         o << "            dq[" << b[1] << "] -= ctb * kb * (X[" << b[0] << "] * X[" << b[2] << "]);\n";
         o << "            dq[" << b[2] << "] -= ctb * kb * (X[" << b[0] << "] * X[" << b[1] << "]);\n";
-        o << "            const double dl = dq[" << nt << "] * m->invM[" << nt << "];\n";
+        o << "            const double dl = dq[" << nt << "] * " << lit(d.invM[nt]) << ";\n";
         for (int k = 0; k < nt; ++k) {
             if (d.dnu[i][k] == 0) continue;
             for (int q2 = 0; q2 < nt; ++q2)
-                o << "            J[" << k << "][" << q2 << "] += m->Mdnu[" << I << "][" << k << "] * (dq[" << q2
-                  << "] * m->invM[" << q2 << "] - dl);\n";
+                o << "            J[" << k << "][" << q2 << "] += " << lit(d.Mdnu[i][k]) << " * (dq[" << q2
+                  << "] * " << lit(d.invM[q2]) << " - dl);\n";
         }
         o << "        }\n";
     }
@@ -169,18 +182,18 @@ std::string adj_chem_spec_source(const DevMech& d) {
         const int* b = d.lb[i];
         const std::string I = std::to_string(i);
         o << "        {  // reaction " << i << "\n            double ci = 0.0;\n";
-        for (int k = 0; k < nt; ++k) o << "            ci += mu[" << k << "] * m->Mdnu[" << I << "][" << k << "];\n";
+        for (int k = 0; k < nt; ++k) o << "            ci += mu[" << k << "] * " << lit(d.Mdnu[i][k]) << ";\n";
         o << "            if (ci != 0.0) {\n";
-        o << "                const double lnkf = m->lnA[" << I << "] + m->b[" << I << "] * lnT - m->EaR[" << I << "] * invT;\n";
+        o << "                const double lnkf = " << lit(d.lnA[i]) << " + " << lit(d.b[i]) << " * lnT - " << lit(d.EaR[i]) << " * invT;\n";
         o << "                const double kf = exp(lnkf);\n                double kb = 0.0, dlb = 0.0;\n";
-        o << "                const double dlf = (m->b[" << I << "] + m->EaR[" << I << "] * invT) * invT;\n";
+        o << "                const double dlf = (" << lit(d.b[i]) << " + " << lit(d.EaR[i]) << " * invT) * invT;\n";
         if (d.rev[i]) {
             o << "                {\n                    double sg = 0.0, sh = 0.0;\n";
             for (int q = 0; q < MAXLIST; ++q) {
                 o << "                    sg += gts[" << b[q] << "] - gts[" << f[q] << "];\n";
                 o << "                    sh += hm1[" << b[q] << "] - hm1[" << f[q] << "];\n";
             }
-            o << "                    kb = exp(lnkf + sg - (double)m->dnsum[" << I << "] * lnC);\n";
+            o << "                    kb = exp(lnkf + sg - " << lit((double)d.dnsum[i]) << " * lnC);\n";
             o << "                    dlb = dlf - sh * invT;\n                }\n";
         }
         // R = k x0 x1 x2, dR/dx_s, dR . dX and its gradient, for the reactants (F) and,
@@ -211,8 +224,8 @@ std::string adj_chem_spec_source(const DevMech& d) {
         if (d.has_tb[i]) {
             o << "                double ctb = 0.0, dctb = 0.0;\n";
             for (int j = 0; j < ns; ++j) {
-                o << "                ctb += m->tb[" << I << "][" << j << "] * X[" << j << "];\n";
-                o << "                dctb += m->tb[" << I << "][" << j << "] * dX[" << j << "];\n";
+                o << "                ctb += " << lit(d.tb[i][j]) << " * X[" << j << "];\n";
+                o << "                dctb += " << lit(d.tb[i][j]) << " * dX[" << j << "];\n";
             }
         } else {
             o << "                const double ctb = 1.0, dctb = 0.0;\n";
@@ -220,7 +233,7 @@ std::string adj_chem_spec_source(const DevMech& d) {
         o << "                const double net = RF - RB, dnet = dRFd - dRBd;\n";
         if (d.has_tb[i])
             for (int j = 0; j < ns; ++j)
-                o << "                G[" << j << "] += ci * m->tb[" << I << "][" << j << "] * (net + dnet);\n";
+                o << "                G[" << j << "] += ci * " << lit(d.tb[i][j]) << " * (net + dnet);\n";
         for (int q = 0; q < 3; ++q) {
             o << "                G[" << f[q] << "] += ci * ((ctb + dctb) * dRF" << q << " + ctb * ddRF" << q << ");\n";
             o << "                G[" << b[q] << "] -= ci * ((ctb + dctb) * dRB" << q << " + ctb * ddRB" << q << ");\n";
