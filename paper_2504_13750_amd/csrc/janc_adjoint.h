@@ -363,9 +363,12 @@ __device__ __forceinline__ void split_flux(const double (&V)[NU], double vn, dou
 
 // B: per interface and component, mu_Fhat = b dt (mu_right - mu_left)/dx and
 // the reverse of both WENO5 reconstructions; the six stencil states and their
-// split fluxes are formed here from the stage input (component = blockIdx.y).
-template <int M, int NU, int F>
-__device__ __forceinline__ void iface_component(const AdjArgs& A, int q) {
+// split fluxes are formed here from the stage input (component F = blockIdx.y). F is
+// a run-time value, uniform over the workgroup: one body serves every component (a
+// body per component made the kernel of the 12-field model copy its arguments to
+// scratch memory, 304 bytes per lane, written by every thread at entry).
+template <int M, int NU>
+__device__ __forceinline__ void iface_component(const AdjArgs& A, int q, const int F) {
     const AdjGrid& g = A.g;
     const int nix = (g.nx + 1) * g.ny, niy = g.twod ? g.nx * (g.ny + 1) : 0;
     if (q >= nix + niy) return;
@@ -420,18 +423,10 @@ __device__ __forceinline__ void iface_component(const AdjArgs& A, int q) {
     }
 }
 
-template <int M, int NU, int F>
-__device__ __forceinline__ void iface_dispatch(const AdjArgs& A, int q, int comp) {
-    if constexpr (F < NU) {
-        if (comp == F) iface_component<M, NU, F>(A, q);
-        else iface_dispatch<M, NU, F + 1>(A, q, comp);
-    }
-}
-
 template <int M, int NU>
 __global__ __launch_bounds__(AWG) void adj_iface(AdjArgs A) {
     const int q = blockIdx.x * AWG + threadIdx.x;
-    iface_dispatch<M, NU, 0>(A, q, (int)blockIdx.y);
+    iface_component<M, NU>(A, q, (int)blockIdx.y);
 }
 
 // Gather of the split-flux adjoints of strip position xi (x sweep: row j, xi in
