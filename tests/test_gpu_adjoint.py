@@ -4,7 +4,8 @@ central finite differences.
 * dL/dQ and dL/dEa against the oracle's dual-number tangents (<= 1e-10 relative);
 * <dL/dW0, v> along seeded directions against the oracle's tangent (<= 1e-10);
 * the full gradient of a 1-3 step trajectory on an 8 x 4 grid, element by
-  element, against oracle tangents along every basis direction;
+  element, against oracle tangents along every basis direction, for three sets of
+  boundary rules (every ghost rule in both sweeps);
 * central differences (h = 1e-6 relative) of the GPU loss on Q and Ea at the full
   adjoint workload (<= 1e-5);
 * the checkpoint interval does not change the result (bitwise);
@@ -17,7 +18,7 @@ import pytest
 
 import oracle
 import paper_2504_13750_amd as janc
-from cases import adjoint_case, detonation_tube_case
+from cases import adjoint_case, detonation_tube_case, BC_PERIODIC, BC_SLIPWALL, BC_ZEROGRAD, BC_DIRICHLET
 from gpu_util import torch_dev
 
 pytestmark = pytest.mark.gpu
@@ -83,9 +84,21 @@ def test_directional_gradient_matches_oracle(field):
     assert got == pytest.approx(dv, rel=1e-10, abs=0.0)
 
 
+# boundary sets (W, E, S, N): the tube's; periodic everywhere; slip wall W, zero-gradient
+# E, a Dirichlet inflow S (the fresh state) and zero-gradient N -- every ghost rule on
+# both sweeps, with the ghost positions that one cell owns merged per side
+_BCS = {"tube": None,
+        "periodic": ([BC_PERIODIC] * 4, [None] * 4),
+        "mixed": ([BC_SLIPWALL, BC_ZEROGRAD, BC_DIRICHLET, BC_ZEROGRAD],
+                  [None, None, np.array([1.0, 0.0, 0.1, 1.0, 1.0]), None])}
+
+
+@pytest.mark.parametrize("bcs", ["tube", "periodic", "mixed"])
 @pytest.mark.parametrize("nsteps", [1, 3])
-def test_full_gradient_brute_force_tiny_grid(nsteps):
+def test_full_gradient_brute_force_tiny_grid(nsteps, bcs):
     c, _, _ = _small(nx=8, ny=4)
+    if _BCS[bcs] is not None:
+        c.bc, c.bc_prim = list(_BCS[bcs][0]), list(_BCS[bcs][1])
     c.W[3] = 1.0 + 0.3 * np.random.default_rng(5).uniform(size=c.W.shape[1:])  # no ties in max
     c.W[0] = 1.0 + 0.2 * np.random.default_rng(6).uniform(size=c.W.shape[1:])
     c.W[1] = 0.1 * np.random.default_rng(7).normal(size=c.W.shape[1:])
@@ -101,7 +114,7 @@ def test_full_gradient_brute_force_tiny_grid(nsteps):
                 ref[f, j, i] = oracle.loss_tangent(c, c.W, nsteps, probes, w, c.dt_fixed, dW0=e)[1]
     scale = np.max(np.abs(ref))
     err = np.max(np.abs(gW - ref)) / scale
-    print(f"  brute force {nsteps} steps: max |g - ref| / max|ref| = {err:.2e}", flush=True)
+    print(f"  brute force {bcs} {nsteps} steps: max |g - ref| / max|ref| = {err:.2e}", flush=True)
     assert err <= 1e-10
 
 
