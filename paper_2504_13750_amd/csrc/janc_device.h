@@ -330,6 +330,21 @@ __device__ __forceinline__ bool covered_by_finer(const StageArgs& a, CDom& D, in
     return a.maps[D.map_off[lev + 1] + (J2 >> 3) * D.map_w[lev + 1] + (I2 >> 3)] >= 0;
 }
 
+// Level-lev cell (I, J) lies under a finer valid block and none of its four children is
+// a coarse-fine ring cell of that block: the restriction replaces it by the mean of its
+// children without reading it. (Fine blocks sit on even cells, so the 2 x 2 children
+// belong to one block.)
+__device__ __forceinline__ bool restricted_over(const StageArgs& a, CDom& D, int lev, int I, int J) {
+    if (lev + 1 >= D.nlevels || !D.twod) return false;
+    const int I2 = 2 * I, J2 = 2 * J;
+    const int b = a.maps[D.map_off[lev + 1] + (J2 >> 3) * D.map_w[lev + 1] + (I2 >> 3)];
+    if (b < 0) return false;
+    const DevBlock& F = a.blk[b];
+    const int li = I2 - F.i0, lj = J2 - F.j0;
+    return !ring_at(F, li, lj) && !ring_at(F, li + 1, lj) && !ring_at(F, li, lj + 1) &&
+           !ring_at(F, li + 1, lj + 1);
+}
+
 // The dispatcher deals the workgroups of a launch round-robin over the 8 XCDs,
 // each with its own L2. Workgroup b of n is given tile chunk(b) so that each XCD
 // walks one contiguous run of tiles: neighbouring tiles, whose halos overlap,

@@ -668,6 +668,15 @@ __device__ __forceinline__ void chem_body(const StageArgs& a, double* scratch, C
     if (phase == 2)   // buffer 3 was read by stage 1; clean for the next step's first half
         for (int q = threadIdx.x; q < a.red.stride; q += WG) a.red.buf[slot_word(a.red.stride, 3, q)] = 0ull;
     if (!(dt > 0.0)) return;
+    // A cell under a finer block is overwritten by the restriction that follows this
+    // launch (the Lie step, or the second half of the Strang split; in the crossover
+    // advance, the level's last step) and leaves the maxima (the restriction publishes
+    // the restricted cell's instead). Where none of its four children is a ring cell,
+    // the restriction does not read it either: its chemistry is dead work.
+    const bool covered = r.own && phase != 1 && B.fine_child && (!a.cross || a.xskip_cov) &&
+                         covered_by_finer(a, D, lev, r.I, r.J);
+    const bool dead = covered && restricted_over(a, D, lev, r.I, r.J);
+    const bool work = r.own && !dead;
     double sx = 0.0, sy = 0.0, sc = 0.0;
     unsigned st = 0u;
     double dY[NS - 1];
@@ -678,15 +687,15 @@ __device__ __forceinline__ void chem_body(const StageArgs& a, double* scratch, C
         double rY[NS - 1];
 #pragma unroll
         for (int k = 0; k < NS - 1; ++k) rY[k] = 0.0;
-        if (r.own) {
+        if (work) {
             rho = a.Uout[r.c];
 #pragma unroll
             for (int k = 0; k < NS - 1; ++k) rY[k] = a.Uout[(size_t)(4 + k) * a.pool + r.c];
             T = a.Tout[r.c];
         }
-        cell(mech, rho, T, rY, dt, dY, st);
+        if (__any(work)) cell(mech, rho, T, rY, dt, dY, st);   // wavefronts with no work skip it
     }
-    if (r.own) {
+    if (work) {
         double u[NU];
 #pragma unroll
         for (int f = 0; f < NU; ++f) u[f] = a.Uout[(size_t)f * a.pool + r.c];
@@ -700,9 +709,7 @@ __device__ __forceinline__ void chem_body(const StageArgs& a, double* scratch, C
         a.Tout[r.c] = Tn;
         if (st) atomicOr(a.status, st);
         // the first half's maxima are stage 1's alpha over all solved cells
-        const bool skip = phase != 1 && B.fine_child && (!a.cross || a.xskip_cov) &&
-                          covered_by_finer(a, D, lev, r.I, r.J);
-        if (!st && !skip) {
+        if (!st && !covered) {
             sx = fabs(vx) + c;
             sy = fabs(vy) + c;
             sc = cfl_bound(a, D, lev, sx, sy, idx, idy);
