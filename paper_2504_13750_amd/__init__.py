@@ -199,7 +199,8 @@ class Plan:
 
 def chem_kernel_check(mech):
     """janc_chem_kernel_check: generate and compile (hipRTC, no device) the chemistry
-    kernel specialised to `mech`; returns (status, compiler log)."""
+    kernels specialised to `mech` (the forward point-implicit step and its reverse in the
+    adjoint); returns (status, compiler log)."""
     m = _Mech(mech)
     buf = C.create_string_buffer(1 << 16)
     st = L.lib().janc_chem_kernel_check(C.byref(m.s), buf, len(buf))
@@ -227,7 +228,9 @@ class Context:
 
     @property
     def chem_kernel(self):
-        """janc_get_chem_kernel: CHEM_GENERIC or CHEM_SPECIALIZED."""
+        """janc_get_chem_kernel: CHEM_GENERIC or CHEM_SPECIALIZED (the default of a
+        detailed-model context once its specialised kernel is built; the forward step and
+        the adjoint's reversed chemistry follow it, with bitwise the same results)."""
         mode = C.c_int()
         self._check(L.lib().janc_get_chem_kernel(self.h, C.byref(mode)))
         return mode.value
