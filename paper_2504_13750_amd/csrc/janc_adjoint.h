@@ -499,12 +499,14 @@ __device__ __forceinline__ void split_vjp(const double (&V)[NU], const PState<NU
     pQ = kp * P.dpQ;
 }
 
-// Adjoint of one strip position (own or ghost) and its contributions.
+// The split-flux adjoints mp, mm gathered at a strip position, applied to the state
+// there (the cell src, mirrored by fl, or a Dirichlet row): out (if add), the alpha
+// and Q parts.
 template <int M, int NU>
-__device__ __forceinline__ void strip_adjoint(const AdjArgs& A, bool xdir, int i, int j, int pos,
-                                              long long src, unsigned fl, const double (&Vc)[NU],
-                                              double Tc, double (&out)[NU], bool add, double& pal,
-                                              double& pQ) {
+__device__ __forceinline__ void strip_apply(const AdjArgs& A, bool xdir, long long src, unsigned fl,
+                                            const double (&Vc)[NU], double Tc, const double (&mp)[NU],
+                                            const double (&mm)[NU], double (&out)[NU], bool add,
+                                            double& pal, double& pQ) {
     const AdjGrid& g = A.g;
     double Vs[NU], Ts = Tc;
     if (src >= 0) {
@@ -518,8 +520,7 @@ __device__ __forceinline__ void strip_adjoint(const AdjArgs& A, bool xdir, int i
         for (int f = 0; f < NU; ++f) Vs[f] = row[f];
         Ts = row[MAXF];
     }
-    double mp[NU], mm[NU], o[NU], pa, pq;
-    gather_strip<NU>(A, xdir, i, j, pos, mp, mm);
+    double o[NU], pa, pq;
     PState<NU> P;
     pstate<M, NU, false>(g, cmech(A.mech), Vs, Ts, P);
     split_vjp<NU>(Vs, P, xdir, A.alpha[xdir ? 0 : 1], mp, mm, o, pa, pq);
@@ -538,6 +539,58 @@ __device__ __forceinline__ void strip_adjoint(const AdjArgs& A, bool xdir, int i
             out[f] += v;
         }
     }
+}
+
+// Adjoint of the cell's own strip position and its contributions.
+template <int M, int NU>
+__device__ __forceinline__ void strip_adjoint(const AdjArgs& A, bool xdir, int i, int j, int pos,
+                                              long long src, unsigned fl, const double (&Vc)[NU],
+                                              double Tc, double (&out)[NU], bool add, double& pal,
+                                              double& pQ) {
+    double mp[NU], mm[NU];
+    gather_strip<NU>(A, xdir, i, j, pos, mp, mm);
+    strip_apply<M, NU>(A, xdir, src, fl, Vc, Tc, mp, mm, out, add, pal, pQ);
+}
+
+// The ghost positions on one side (0: low, 1: high) of the cell's row (x sweep) or
+// column (y sweep) that this cell owns: those whose source is the cell, or, on the first
+// or last cell, the side's Dirichlet row. All of them have the same state (the same
+// source and mirror flags, or the same row), and the reverse of the split is linear in
+// the gathered adjoints, so their gathers are summed (in position order) and applied
+// once: one state evaluation per side instead of one per position.
+template <int M, int NU>
+__device__ __forceinline__ void ghost_side(const AdjArgs& A, bool xdir, int i, int j, int side,
+                                           long long c, const double (&Vc)[NU], double Tc,
+                                           double (&out)[NU], double& pal, double& pQ) {
+    const AdjGrid& g = A.g;
+    const int len = xdir ? g.nx : g.ny;
+    const int own = xdir ? i : j;
+    double mp[NU], mm[NU];
+#pragma unroll
+    for (int f = 0; f < NU; ++f) mp[f] = mm[f] = 0.0;
+    bool any = false;
+    long long s0 = 0;
+    unsigned f0 = 0u;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int gp = (side == 0) ? -1 - k : len + k;
+        unsigned fl;
+        const long long s = xdir ? usrc(g, gp, j, fl) : usrc(g, i, gp, fl);
+        const bool owner = (s == c) || (s < 0 && own == ((side == 0) ? 0 : len - 1));
+        if (owner) {
+            double ap[NU], am[NU];
+            gather_strip<NU>(A, xdir, xdir ? gp : i, xdir ? j : gp, gp + 3, ap, am);
+#pragma unroll
+            for (int f = 0; f < NU; ++f) {
+                mp[f] += ap[f];
+                mm[f] += am[f];
+            }
+            any = true;
+            s0 = s;
+            f0 = fl;
+        }
+    }
+    if (any) strip_apply<M, NU>(A, xdir, s0, f0, Vc, Tc, mp, mm, out, s0 == c, pal, pQ);
 }
 
 // C: per interior cell, the adjoint of the stage input: its own x and y strip
@@ -571,24 +624,14 @@ __global__ __launch_bounds__(AWG) void adj_cell(AdjArgs A) {
             for (int f = 0; f < NU; ++f) out[f] = A.b * A.lamW[(size_t)f * A.n + c];
             strip_adjoint<M, NU>(A, true, i, j, i + 3, c, 0u, V, Tc, out, true, pax, pQ);
             if (i < 3 || i >= g.nx - 3) {
-                for (int gq = 0; gq < 6; ++gq) {
-                    const int gi = (gq < 3) ? -1 - gq : g.nx + gq - 3;
-                    unsigned fl;
-                    const long long s = usrc(g, gi, j, fl);
-                    const bool owner = (s == c) || (s < 0 && i == ((gq < 3) ? 0 : g.nx - 1));
-                    if (owner) strip_adjoint<M, NU>(A, true, gi, j, gi + 3, s, fl, V, Tc, out, s == c, pax, pQ);
-                }
+                ghost_side<M, NU>(A, true, i, j, 0, c, V, Tc, out, pax, pQ);
+                ghost_side<M, NU>(A, true, i, j, 1, c, V, Tc, out, pax, pQ);
             }
         } else if (g.twod) {
             strip_adjoint<M, NU>(A, false, i, j, j + 3, c, 0u, V, Tc, out, true, pay, pQ);
             if (j < 3 || j >= g.ny - 3) {
-                for (int gq = 0; gq < 6; ++gq) {
-                    const int gj = (gq < 3) ? -1 - gq : g.ny + gq - 3;
-                    unsigned fl;
-                    const long long s = usrc(g, i, gj, fl);
-                    const bool owner = (s == c) || (s < 0 && j == ((gq < 3) ? 0 : g.ny - 1));
-                    if (owner) strip_adjoint<M, NU>(A, false, i, gj, gj + 3, s, fl, V, Tc, out, s == c, pay, pQ);
-                }
+                ghost_side<M, NU>(A, false, i, j, 0, c, V, Tc, out, pay, pQ);
+                ghost_side<M, NU>(A, false, i, j, 1, c, V, Tc, out, pay, pQ);
             }
         }
     }
