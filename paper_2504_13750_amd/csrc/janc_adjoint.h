@@ -703,13 +703,20 @@ __global__ __launch_bounds__(AWG) void adj_finish(AdjArgs A) {
     const int T = nal + nsd;
     const int k = threadIdx.x;
     // The state at the cell of this thread's task (an alpha term at its argmax cell, or a
-    // probe's loss seed) does not depend on the block partials: it is loaded first, so
-    // that its latency overlaps the reduction.
+    // probe's loss seed) does not depend on the block partials, and neither do the
+    // adjoints there that the task adds to, nor theta: they are loaded first, so that
+    // their latency overlaps the reduction. (Only this kernel writes them meanwhile, each
+    // cell from one thread: the one whose own task cell it is.)
     long long cell = -1;
-    double Vc[NU];
+    double Vc[NU], lo[NU], ao[NU];
     double Tc = 0.0;
 #pragma unroll
-    for (int f = 0; f < NU; ++f) Vc[f] = 0.0;
+    for (int f = 0; f < NU; ++f) Vc[f] = lo[f] = ao[f] = 0.0;
+    double th0 = 0.0, th1 = 0.0;
+    if (k == 0) {
+        th0 = A.theta[0];
+        th1 = A.theta[1];
+    }
     if (k < T) {
         if (k < nal) {
             const long long ca = A.argm[k];
@@ -720,7 +727,11 @@ __global__ __launch_bounds__(AWG) void adj_finish(AdjArgs A) {
         if (cell >= 0) {
             const double* src = (k < nal) ? A.V : A.seedU;
 #pragma unroll
-            for (int f = 0; f < NU; ++f) Vc[f] = src[(size_t)f * A.n + cell];
+            for (int f = 0; f < NU; ++f) {
+                Vc[f] = src[(size_t)f * A.n + cell];
+                lo[f] = A.lamOut[(size_t)f * A.n + cell];
+                ao[f] = A.acc[(size_t)f * A.n + cell];
+            }
             if (M == DETAILED) Tc = (k < nal) ? A.VT[cell] : A.seedT[cell];
         }
     }
@@ -812,19 +823,19 @@ __global__ __launch_bounds__(AWG) void adj_finish(AdjArgs A) {
                     sa[f] += dacc[q][f];
                 }
             }
-            const long long cc = tc[k];
+            const long long cc = tc[k];   // = cell, whose adjoints this thread loaded
 #pragma unroll
             for (int f = 0; f < NU; ++f) {
-                if (ul) A.lamOut[(size_t)f * A.n + cc] += sl[f];
-                A.acc[(size_t)f * A.n + cc] += sa[f];
+                if (ul) A.lamOut[(size_t)f * A.n + cc] = lo[f] + sl[f];
+                A.acc[(size_t)f * A.n + cc] = ao[f] + sa[f];
             }
         }
     }
     if (threadIdx.x == 0) {
         double sQ = red[2];
         for (int q = 0; q < T; ++q) sQ += dth[q];
-        A.theta[0] += sQ;
-        A.theta[1] += red[3];
+        A.theta[0] = th0 + sQ;
+        A.theta[1] = th1 + red[3];
     }
 }
 
